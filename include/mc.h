@@ -1,0 +1,247 @@
+/*
+ * mc.h -- C ABI of libmc, a fixed-step simulator of the layered cortical
+ * microcircuit (8 populations, 77,169 neurons and ~3e8 synapses at full scale)
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The model follows Rhodes et al., "Real-Time Cortical Simulation on Neuromorphic
+ * Hardware" (arXiv 1909.08665): Sec. 2a and Eq. 1 define the neuron (leaky
+ * integrate-and-fire, current-based exponential synapses, reset on threshold
+ * crossing), the weight and delay distributions and the Poisson background;
+ * Sec. 3a(ii) defines the synaptic matrix (rows indexed by presynaptic neuron,
+ * each word = target, weight, delay) and the per-neuron synaptic input buffers
+ * (255 slots, the slot for t + delay receives the weight); Sec. 3c defines a
+ * synaptic event (one spike reaching one postsynaptic synapse).
+ *
+ * Each simulation step (dt = 0.1 ms) runs entirely on the GPU:
+ *   1. read and clear every neuron's input-buffer slot for this step, add the
+ *      step's Poisson background count times the background weight;
+ *   2. exact-integration LIF update;
+ *   3. threshold test, reset, spike compaction and recording;
+ *   4. delivery of each spiking neuron's synaptic row into the targets' delay
+ *      ring buffers (int32, 1/256 pA fixed point, integer atomics).
+ *
+ * Conventions for every call:
+ *   - every call returns MC_OK (0) or a negative MC_ERR_* code; on error,
+ *     mc_last_error() returns a message (thread-local, valid until the next call
+ *     on the same thread); no C++ exception crosses this interface;
+ *   - all pointers in the signatures are HOST pointers owned by the caller,
+ *     read or written only during the call;
+ *   - an mc_net owns all of its device memory and its HIP stream; it is not
+ *     thread-safe: one thread at a time per handle;
+ *   - neuron ids are instance-local and ordered by population:
+ *     L2/3E, L2/3I, L4E, L4I, L5E, L5I, L6E, L6I;
+ *   - a spike time is the integer step index n (t = n * dt).
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define MC_OK 0
+#define MC_ERR_ARG (-1)              /* invalid argument or configuration */
+#define MC_ERR_NOMEM (-2)            /* host or device allocation failed */
+#define MC_ERR_HIP (-3)              /* a HIP runtime call failed */
+#define MC_ERR_OVERFLOW_BOUND (-4)   /* int32 input-buffer bound exceeded at build */
+#define MC_ERR_DELAY_RANGE (-5)      /* a delay outside [1, 255] steps */
+#define MC_ERR_RECORD_OVERFLOW (-6)  /* device spike recorder overflowed during a run */
+#define MC_ERR_BUFFER_TOO_SMALL (-7) /* caller buffer too small; nothing consumed */
+#define MC_ERR_IO (-8)               /* checkpoint file could not be read/written */
+#define MC_ERR_UNSUPPORTED (-9)      /* requested engine cannot run this network */
+
+/* Synaptic weight store (Sec. 2a weights; reduced-precision forms). */
+#define MC_W_FP32 0   /* float weight holding the 1/256 pA fixed-point value */
+#define MC_W_FP16 1   /* IEEE binary16, round-to-nearest-even from double */
+#define MC_W_BF16 2   /* bfloat16, round-to-nearest-even from double */
+
+/* Step engines.  All give bit-identical results. */
+#define MC_ENGINE_AUTO 0    /* TILED when the network fits, else GRAPH */
+#define MC_ENGINE_GRAPH 1   /* two kernels per step, K steps captured in a hipGraph */
+#define MC_ENGINE_TILED 2   /* persistent kernel, LDS-resident ring per neuron tile */
+
+#define MC_NPOP 8
+
+/*
+ * Model and run configuration.  Initialise with mc_config_default(), then set
+ * conn_probs (required: the 8x8 table has no default).  Parameter defaults are
+ * those of Sec. 2a of the paper with the workload's delay values.
+ */
+typedef struct mc_config {
+    uint32_t struct_size;        /* sizeof(mc_config), set by mc_config_default */
+    const double *conn_probs;    /* [64] conn_probs[8*a + b] = probability that a given
+                                    (pre in population a, post in population b) pair is
+                                    connected; each in [0, 1).  Required. */
+    int32_t wfmt;                /* MC_W_FP32 | MC_W_FP16 | MC_W_BF16 */
+    int32_t poisson_on;          /* 1: Poisson background drive (default); 0: none */
+    int32_t init_mode;           /* 0: u ~ U[0, theta) (default); 1: u = 0 */
+    int32_t engine;              /* MC_ENGINE_* */
+    int64_t record_capacity;     /* device recorder entries; 0 = automatic */
+    double full_size[MC_NPOP];   /* full-scale population sizes */
+    double k_ext[MC_NPOP];       /* Poisson in-degree per population */
+    double i_dc_pa[MC_NPOP];     /* constant input current per population (0) */
+    double nu_bg_hz;             /* background rate per source: 8 Hz */
+    double dt_ms;                /* 0.1 */
+    double tau_m_ms;             /* 10 */
+    double c_m_pf;               /* 250 */
+    double tau_syn_ms;           /* 0.5 */
+    double t_ref_ms;             /* 2 */
+    double theta_mv;             /* V_th - E_L = 15 */
+    double w_mean_pa;            /* 87.8 */
+    double w_sd_pa;              /* 8.78 */
+    double g;                    /* inhibitory weight factor: -4 */
+    double l4e_l23e_factor;      /* mean factor for L4E -> L2/3E: 2 */
+    double w_ext_pa;             /* background weight: 87.8 */
+    double d_mean_exc_ms, d_sd_exc_ms;   /* 1.5, 0.75 */
+    double d_mean_inh_ms, d_sd_inh_ms;   /* 0.8, 0.4 */
+} mc_config;
+
+typedef struct mc_counters {
+    int64_t steps;               /* steps simulated so far */
+    int64_t spikes;              /* spikes emitted (recurrent sources) */
+    int64_t events;              /* synaptic events: sum of out-degrees of spiking neurons (Sec. 3c) */
+    int64_t poisson_events;      /* background spikes drawn (whole network, all instances) */
+    int64_t max_spikes_per_step; /* largest spike count in one step (whole network) */
+} mc_counters;
+
+typedef struct mc_info {
+    int32_t n_instances;
+    int32_t ring_depth;          /* R: power of two > the largest delay */
+    int32_t engine;              /* engine selected for mc_run */
+    int32_t wfmt;
+    int64_t n_neurons;           /* all instances */
+    int64_t n_synapses;          /* all instances */
+    int32_t tile_neurons;        /* TILED engine: neurons per workgroup tile (0 otherwise) */
+    int32_t n_tiles;
+    int32_t graph_chunk;         /* GRAPH engine: steps per captured graph */
+    int32_t seg;                 /* GRAPH engine: synapses per delivery work item */
+    int32_t block;               /* GRAPH engine: threads per block of the neuron kernel */
+    int32_t deliver_grid;        /* GRAPH engine: blocks of the delivery kernel */
+} mc_info;
+
+/* Launch knobs chosen by the autotuner or set by hand (0 = keep current). */
+typedef struct mc_launch {
+    int32_t engine;
+    int32_t graph_chunk;         /* 1..1024 */
+    int32_t seg;                 /* 64, 128, 256 or 512 */
+    int32_t block;               /* 64, 128, 256 or 512 */
+    int32_t deliver_grid;        /* >= 1 */
+} mc_launch;
+
+/* Fill *cfg with the defaults of Sec. 2a; conn_probs is left NULL. */
+int mc_config_default(mc_config *cfg);
+
+/*
+ * Build one microcircuit instance at `scale` (0, 1] from `seed` and upload it.
+ * Population sizes are floor(N_full * scale + 0.5) (at least 1).  For each
+ * ordered population pair a fixed total of K = log(1-p)/log(1-1/(N_a N_b))
+ * synapses (rounded) is drawn with uniform pre and post (multapses allowed),
+ * normal weights and delays as in Sec. 2a (delays rounded to steps, clipped to
+ * [1, 255], the buffer length of Sec. 3a(ii)); random numbers from
+ * Philox4x64-10 keyed (seed, 0).  Untimed set-up.
+ * On success *out owns the network; release with mc_free().
+ * Errors: MC_ERR_ARG, MC_ERR_NOMEM, MC_ERR_HIP, MC_ERR_OVERFLOW_BOUND.
+ */
+int mc_build_network(uint64_t seed, double scale, const mc_config *cfg, struct mc_net **out);
+
+/*
+ * Build `n` independent instances (seeds[i], scales[i]) as disjoint blocks of one
+ * network advanced by the same kernels; instance i behaves exactly as the
+ * single network built with (seeds[i], scales[i]).  Errors as mc_build_network.
+ */
+int mc_build_batch(const uint64_t *seeds, const double *scales, int32_t n,
+                   const mc_config *cfg, struct mc_net **out);
+
+/*
+ * Advance the network by `steps` steps (synchronous: returns when the GPU is done).
+ * mc_run(a); mc_run(b) gives bit-identical results to mc_run(a + b).
+ * Errors: MC_ERR_ARG (steps < 0), MC_ERR_HIP, MC_ERR_RECORD_OVERFLOW (the spikes
+ * that did not fit are lost; counters still count them).
+ */
+int mc_run(struct mc_net *net, int64_t steps);
+
+/*
+ * Copy out and consume the spikes of `instance` recorded since the previous call,
+ * sorted by (step, id).  steps_out/ids_out have room for `cap` entries;
+ * *count_out receives the number of spikes.  If cap is too small, returns
+ * MC_ERR_BUFFER_TOO_SMALL with *count_out = the number needed and consumes nothing.
+ */
+int mc_get_spikes(struct mc_net *net, int32_t instance, int64_t *steps_out, int32_t *ids_out,
+                  int64_t cap, int64_t *count_out);
+
+/*
+ * Copy the state of `instance`: u = V - E_L in mV, synaptic current in pA,
+ * remaining refractory steps.  Any output pointer may be NULL.  `n` must equal
+ * the instance's neuron count (MC_ERR_ARG otherwise).
+ */
+int mc_get_state(struct mc_net *net, int32_t instance, float *u_mv, float *i_pa, int32_t *refr, int64_t n);
+
+/* Overwrite the state of `instance` (same layout as mc_get_state; NULL = keep). */
+int mc_set_state(struct mc_net *net, int32_t instance, const float *u_mv, const float *i_pa,
+                 const int32_t *refr, int64_t n);
+
+/*
+ * Counters of `instance` (spikes, events) over the spikes recorded so far;
+ * instance = -1 gives the whole network.  poisson_events and
+ * max_spikes_per_step are always whole-network values.
+ */
+int mc_get_counters(struct mc_net *net, int32_t instance, mc_counters *out);
+
+/* Sizes and the launch configuration in use. */
+int mc_get_info(struct mc_net *net, mc_info *out);
+
+/*
+ * Copy the synapse store of `instance` back from the GPU, with instance-local
+ * target ids: row_ptr [N+1] (int64), post [M], wq [M] (weight in 1/256 pA as
+ * int32), d [M] (delay in steps).  Rows are ordered by presynaptic neuron.
+ * Any output may be NULL.  `n_synapses` must equal the instance's synapse count.
+ */
+int mc_get_csr(struct mc_net *net, int32_t instance, int64_t *row_ptr, int32_t *post, int32_t *wq,
+               uint8_t *d, int64_t n_synapses);
+
+/* Number of neurons and synapses of `instance`. */
+int mc_instance_size(struct mc_net *net, int32_t instance, int64_t *n_neurons, int64_t *n_synapses);
+
+/* Select launch knobs (engine, graph chunk, work-item size, block, grid). */
+int mc_set_launch(struct mc_net *net, const mc_launch *l);
+
+/*
+ * Autotuner: time each candidate launch configuration for `trial_steps` steps on
+ * a saved copy of the state, restore the state, and keep the fastest.  Results of
+ * later runs do not depend on the choice.
+ */
+int mc_tune(struct mc_net *net, int64_t trial_steps);
+
+/* Use the caller's HIP stream (hipStream_t passed as void*); NULL = own stream. */
+int mc_set_stream(struct mc_net *net, void *hip_stream);
+
+/*
+ * Kernel timing with HIP events on the network's stream: enable (1) or disable (0)
+ * timing of the dominant kernel; mc_get_timing returns the summed duration in ms
+ * and the number of launches timed since it was enabled.
+ */
+int mc_set_timing(struct mc_net *net, int32_t on);
+int mc_get_timing(struct mc_net *net, double *kernel_ms, int64_t *launches);
+
+/*
+ * Checkpoint: write / read the full dynamic state (step counter, neuron state,
+ * input buffers, counters and unread spikes) to / from `path`.  The random
+ * streams are counter-based, so a restored run continues bit-identically.
+ * mc_load_state requires a network built with the same arguments.
+ */
+int mc_save_state(struct mc_net *net, const char *path);
+int mc_load_state(struct mc_net *net, const char *path);
+
+/* Release the network and all of its device memory.  NULL is allowed. */
+void mc_free(struct mc_net *net);
+
+/* Message of the last error on this thread ("" if none). */
+const char *mc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MC_H */

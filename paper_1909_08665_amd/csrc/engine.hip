@@ -1,0 +1,684 @@
+// engine.hip -- device store, step engines and the C ABI of libmc.
+//
+// The GRAPH engine captures K steps (neuron kernel + delivery kernel per step,
+// then a one-thread counter advance) in a hipGraph and replays it; the step
+// index lives in device memory, so the spike count never returns to the host
+// inside a run.  The host drains the spike recorder every `kSegSteps` steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mc.h"
+#include "kernels.hpp"
+#include "model.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(MC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr int64_t kSegSteps = 1000;   // steps between recorder drains
+
+}  // namespace
+
+struct mc_net {
+    mc::ModelParams params{};
+    mc::StepConstants sc{};
+    mc::HostNet host;                  // host copy: sizes, offsets, row pointers
+
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    // device buffers
+    float *u = nullptr, *cur = nullptr;
+    uint8_t *refr = nullptr;
+    uint32_t *meta = nullptr;
+    int32_t *inst_off = nullptr;
+    uint64_t *seeds = nullptr;
+    float *cdc = nullptr;
+    uint64_t *pois_thr = nullptr;
+    int32_t *ring = nullptr;
+    uint64_t *row_ptr = nullptr;
+    int32_t *tgt = nullptr;
+    void *w = nullptr;
+    uint8_t *dly = nullptr;
+    mc::StepCtl *ctl = nullptr;
+    uint64_t *work = nullptr;
+    unsigned long long *pois_acc = nullptr;
+    int64_t pois_slots = 0;
+    int32_t *rec_id = nullptr, *rec_step = nullptr;
+    int64_t rec_cap = 0;
+
+    // pinned staging for recorder drains
+    int32_t *h_rec_id = nullptr, *h_rec_step = nullptr;
+    mc::StepCtl *h_ctl = nullptr;
+
+    // launch configuration
+    int engine = MC_ENGINE_GRAPH;
+    int graph_chunk = 50;
+    int seg = 256;
+    int block = 256;
+    int deliver_grid = 1024;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_k = 0;
+
+    // host-side run state
+    int64_t step = 0;
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;   // per instance
+    std::vector<int64_t> inst_spikes, inst_events;
+    bool overflow = false;
+
+    // kernel timing
+    bool timing = false;
+    double kernel_ms = 0.0;
+    int64_t launches = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+template <class T>
+int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return MC_OK;
+}
+
+mc::DevNet dev_view(const mc_net *nt)
+{
+    mc::DevNet d{};
+    d.n = static_cast<int32_t>(nt->host.n);
+    d.ring_mask = nt->host.ring - 1;
+    d.ref_steps = nt->sc.ref_steps;
+    d.wq_ext = nt->sc.wq_ext;
+    d.p22 = nt->sc.p22;
+    d.p11 = nt->sc.p11;
+    d.p21 = nt->sc.p21;
+    d.theta = nt->sc.theta;
+    d.poisson_on = nt->params.poisson_on;
+    d.seg = nt->seg;
+    d.wfmt = nt->params.wfmt;
+    d.u = nt->u;
+    d.cur = nt->cur;
+    d.refr = nt->refr;
+    d.meta = nt->meta;
+    d.inst_off = nt->inst_off;
+    d.seeds = nt->seeds;
+    d.cdc = nt->cdc;
+    d.pois_thr = nt->pois_thr;
+    d.ring = nt->ring;
+    d.row_ptr = nt->row_ptr;
+    d.tgt = nt->tgt;
+    d.w = nt->w;
+    d.dly = nt->dly;
+    d.ctl = nt->ctl;
+    d.work = nt->work;
+    d.pois_acc = nt->pois_acc;
+    d.rec_id = nt->rec_id;
+    d.rec_step = nt->rec_step;
+    d.rec_cap = nt->rec_cap;
+    return d;
+}
+
+void release(mc_net *nt)
+{
+    if (!nt) return;
+    if (nt->graph_exec) hipGraphExecDestroy(nt->graph_exec);
+    void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
+                    nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
+                    nt->rec_id, nt->rec_step};
+    for (void *b : bufs)
+        if (b) hipFree(b);
+    if (nt->h_rec_id) hipHostFree(nt->h_rec_id);
+    if (nt->h_rec_step) hipHostFree(nt->h_rec_step);
+    if (nt->h_ctl) hipHostFree(nt->h_ctl);
+    if (nt->ev0) hipEventDestroy(nt->ev0);
+    if (nt->ev1) hipEventDestroy(nt->ev1);
+    if (nt->stream && nt->own_stream) hipStreamDestroy(nt->stream);
+    delete nt;
+}
+
+int params_from_config(const mc_config *cfg, mc::ModelParams &p)
+{
+    if (!cfg) return fail(MC_ERR_ARG, "cfg must not be NULL (the connection table has no default)");
+    if (cfg->struct_size != sizeof(mc_config)) return fail(MC_ERR_ARG, "cfg->struct_size mismatch (use mc_config_default)");
+    if (!cfg->conn_probs) return fail(MC_ERR_ARG, "cfg->conn_probs is required");
+    if (cfg->wfmt < MC_W_FP32 || cfg->wfmt > MC_W_BF16) return fail(MC_ERR_ARG, "unknown weight format");
+    if (cfg->engine < MC_ENGINE_AUTO || cfg->engine > MC_ENGINE_TILED) return fail(MC_ERR_ARG, "unknown engine");
+    if (!(cfg->dt_ms > 0) || !(cfg->tau_m_ms > 0) || !(cfg->tau_syn_ms > 0) || !(cfg->c_m_pf > 0))
+        return fail(MC_ERR_ARG, "time constants, capacitance and dt must be positive");
+    if (cfg->tau_m_ms == cfg->tau_syn_ms) return fail(MC_ERR_ARG, "tau_m must differ from tau_syn");
+    std::memcpy(p.conn, cfg->conn_probs, sizeof(p.conn));
+    std::memcpy(p.full_size, cfg->full_size, sizeof(p.full_size));
+    std::memcpy(p.k_ext, cfg->k_ext, sizeof(p.k_ext));
+    std::memcpy(p.i_dc, cfg->i_dc_pa, sizeof(p.i_dc));
+    p.nu_bg_hz = cfg->nu_bg_hz;
+    p.dt_ms = cfg->dt_ms;
+    p.tau_m_ms = cfg->tau_m_ms;
+    p.c_m_pf = cfg->c_m_pf;
+    p.tau_syn_ms = cfg->tau_syn_ms;
+    p.t_ref_ms = cfg->t_ref_ms;
+    p.theta_mv = cfg->theta_mv;
+    p.w_mean_pa = cfg->w_mean_pa;
+    p.w_sd_pa = cfg->w_sd_pa;
+    p.g = cfg->g;
+    p.l4e_l23e_factor = cfg->l4e_l23e_factor;
+    p.w_ext_pa = cfg->w_ext_pa;
+    p.d_mean_exc_ms = cfg->d_mean_exc_ms;
+    p.d_sd_exc_ms = cfg->d_sd_exc_ms;
+    p.d_mean_inh_ms = cfg->d_mean_inh_ms;
+    p.d_sd_inh_ms = cfg->d_sd_inh_ms;
+    p.wfmt = cfg->wfmt;
+    p.poisson_on = cfg->poisson_on ? 1 : 0;
+    p.init_mode = cfg->init_mode;
+    const double ref = p.t_ref_ms / p.dt_ms;
+    if (!(ref >= 0.0 && ref < 255.0)) return fail(MC_ERR_ARG, "refractory time must be below 255 steps");
+    return MC_OK;
+}
+
+int upload(mc_net *nt, const mc_config *cfg)
+{
+    const mc::HostNet &H = nt->host;
+    const int64_t N = H.n, M = H.m;
+    int rc;
+    HIP_TRY(hipGetDevice(&nt->device));
+    HIP_TRY(hipStreamCreateWithFlags(&nt->stream, hipStreamNonBlocking));
+    nt->own_stream = true;
+    HIP_TRY(hipEventCreate(&nt->ev0));
+    HIP_TRY(hipEventCreate(&nt->ev1));
+
+    if ((rc = dalloc(&nt->u, N)) || (rc = dalloc(&nt->cur, N)) || (rc = dalloc(&nt->refr, N)) ||
+        (rc = dalloc(&nt->meta, N)) || (rc = dalloc(&nt->inst_off, H.n_inst + 1)) ||
+        (rc = dalloc(&nt->seeds, H.n_inst)) || (rc = dalloc(&nt->cdc, mc::kPops)) ||
+        (rc = dalloc(&nt->pois_thr, mc::kPops * mc::kPoisMax)) ||
+        (rc = dalloc(&nt->ring, static_cast<size_t>(H.ring) * N)) || (rc = dalloc(&nt->row_ptr, N + 1)) ||
+        (rc = dalloc(&nt->tgt, M)) || (rc = dalloc(&nt->dly, M)) || (rc = dalloc(&nt->ctl, 1)))
+        return rc;
+    const size_t wbytes = nt->params.wfmt == mc::kWFp32 ? 4 : 2;
+    {
+        hipError_t e = hipMalloc(&nt->w, std::max<size_t>(1, M * wbytes));
+        if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    const int64_t work_cap = N + (M + 63) / 64 + 1;
+    if ((rc = dalloc(&nt->work, work_cap))) return rc;
+    nt->pois_slots = (N + 63) / 64 + 1;
+    if ((rc = dalloc(&nt->pois_acc, nt->pois_slots))) return rc;
+    int64_t cap = cfg->record_capacity;
+    if (cap <= 0) cap = std::max<int64_t>(int64_t{1} << 22, 64 * N);
+    nt->rec_cap = cap;
+    if ((rc = dalloc(&nt->rec_id, cap)) || (rc = dalloc(&nt->rec_step, cap))) return rc;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_id), cap * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_step), cap * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl), sizeof(mc::StepCtl), hipHostMallocDefault));
+
+    // Static data.
+    HIP_TRY(hipMemcpy(nt->meta, H.meta.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->inst_off, H.inst_off.data(), (H.n_inst + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->seeds, H.seeds.data(), H.n_inst * sizeof(uint64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->cdc, nt->sc.cdc, sizeof(nt->sc.cdc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->pois_thr, nt->sc.pois_thr, sizeof(nt->sc.pois_thr), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->row_ptr, H.row_ptr.data(), (N + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
+    if (M) {
+        HIP_TRY(hipMemcpy(nt->tgt, H.tgt.data(), M * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(nt->dly, H.d.data(), M, hipMemcpyHostToDevice));
+        if (nt->params.wfmt == mc::kWFp32) {
+            // float holding the fixed-point weight wq / 256 (exact for |wq| < 2^24)
+            const int64_t chunk = int64_t{1} << 24;
+            std::vector<float> tmp(static_cast<size_t>(std::min(M, chunk)));
+            for (int64_t s0 = 0; s0 < M; s0 += chunk) {
+                const int64_t s1 = std::min(M, s0 + chunk);
+                for (int64_t s = s0; s < s1; ++s) tmp[s - s0] = static_cast<float>(H.wq[s]) * 0.00390625f;
+                HIP_TRY(hipMemcpy(static_cast<float *>(nt->w) + s0, tmp.data(), (s1 - s0) * sizeof(float), hipMemcpyHostToDevice));
+            }
+        } else {
+            HIP_TRY(hipMemcpy(nt->w, H.w16.data(), M * sizeof(uint16_t), hipMemcpyHostToDevice));
+        }
+    }
+    // Dynamic state.
+    HIP_TRY(hipMemcpy(nt->u, H.u0.data(), N * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(nt->cur, 0, N * sizeof(float)));
+    HIP_TRY(hipMemset(nt->refr, 0, N));
+    HIP_TRY(hipMemset(nt->ring, 0, static_cast<size_t>(H.ring) * N * sizeof(int32_t)));
+    HIP_TRY(hipMemset(nt->ctl, 0, sizeof(mc::StepCtl)));
+    HIP_TRY(hipMemset(nt->pois_acc, 0, nt->pois_slots * sizeof(unsigned long long)));
+    HIP_TRY(hipDeviceSynchronize());
+    return MC_OK;
+}
+
+int build_common(const uint64_t *seeds, const double *scales, int32_t n, const mc_config *cfg, mc_net **out)
+{
+    if (!out) return fail(MC_ERR_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!seeds || !scales || n < 1) return fail(MC_ERR_ARG, "need at least one (seed, scale)");
+    mc_net *nt = new (std::nothrow) mc_net();
+    if (!nt) return fail(MC_ERR_NOMEM, "out of host memory");
+    int rc = params_from_config(cfg, nt->params);
+    if (rc) { release(nt); return rc; }
+    mc::derive_constants(nt->params, nt->sc);
+    std::string msg;
+    try {
+        rc = mc::build_host_network(nt->params, seeds, scales, n, nt->host, msg);
+    } catch (const std::bad_alloc &) {
+        rc = MC_ERR_NOMEM;
+        msg = "out of host memory";
+    } catch (...) {
+        rc = MC_ERR_ARG;
+        msg = "network build failed";
+    }
+    if (rc) { release(nt); return fail(rc, msg); }
+    rc = upload(nt, cfg);
+    if (rc) { release(nt); return rc; }
+    // Keep only what the host needs after upload.
+    std::vector<int32_t>().swap(nt->host.tgt);
+    std::vector<int32_t>().swap(nt->host.wq);
+    std::vector<uint16_t>().swap(nt->host.w16);
+    std::vector<uint8_t>().swap(nt->host.d);
+    nt->unread.assign(n, {});
+    nt->inst_spikes.assign(n, 0);
+    nt->inst_events.assign(n, 0);
+    nt->engine = cfg->engine == MC_ENGINE_TILED ? MC_ENGINE_TILED : MC_ENGINE_GRAPH;
+    if (nt->engine == MC_ENGINE_TILED) { release(nt); return fail(MC_ERR_UNSUPPORTED, "tiled engine not available"); }
+    *out = nt;
+    return MC_OK;
+}
+
+int instance_of(const mc_net *nt, int32_t gid)
+{
+    const auto &off = nt->host.inst_off;
+    return static_cast<int>(std::upper_bound(off.begin(), off.end(), gid) - off.begin()) - 1;
+}
+
+// Copy the recorder to the host, reset it, check error flags.
+int drain(mc_net *nt)
+{
+    HIP_TRY(hipMemcpyAsync(nt->h_ctl, nt->ctl, sizeof(mc::StepCtl), hipMemcpyDeviceToHost, nt->stream));
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    const int64_t total = nt->h_ctl->rec_total;
+    const int64_t got = std::min(total, nt->rec_cap);
+    if (got > 0) {
+        HIP_TRY(hipMemcpyAsync(nt->h_rec_id, nt->rec_id, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
+        HIP_TRY(hipMemcpyAsync(nt->h_rec_step, nt->rec_step, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
+    }
+    const int64_t zero = 0;
+    const uint32_t zflags = 0;
+    HIP_TRY(hipMemcpyAsync(&nt->ctl->rec_total, &zero, sizeof(zero), hipMemcpyHostToDevice, nt->stream));
+    HIP_TRY(hipMemcpyAsync(&nt->ctl->flags, &zflags, sizeof(zflags), hipMemcpyHostToDevice, nt->stream));
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    const auto &rp = nt->host.row_ptr;
+    for (int64_t q = 0; q < got; ++q) {
+        const int32_t gid = nt->h_rec_id[q];
+        const int inst = nt->host.n_inst == 1 ? 0 : instance_of(nt, gid);
+        nt->unread[inst].emplace_back(static_cast<int64_t>(nt->h_rec_step[q]), gid - nt->host.inst_off[inst]);
+        nt->inst_spikes[inst] += 1;
+        nt->inst_events[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
+    }
+    if (total > nt->rec_cap || (nt->h_ctl->flags & mc::kFlagRecordOverflow)) nt->overflow = true;
+    return MC_OK;
+}
+
+int ensure_graph(mc_net *nt)
+{
+    if (nt->graph_exec && nt->graph_k == nt->graph_chunk) return MC_OK;
+    if (nt->graph_exec) {
+        hipGraphExecDestroy(nt->graph_exec);
+        nt->graph_exec = nullptr;
+    }
+    const mc::DevNet d = dev_view(nt);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(nt->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < nt->graph_chunk && e == hipSuccess; ++s) {
+        e = mc::launch_neuron(d, nt->block, s, nt->stream);
+        if (e == hipSuccess) e = mc::launch_deliver(d, nt->deliver_grid, s, nt->stream);
+    }
+    if (e == hipSuccess) e = mc::launch_advance(d, nt->graph_chunk, nt->stream);
+    hipError_t e2 = hipStreamEndCapture(nt->stream, &g);
+    if (e != hipSuccess) { if (g) hipGraphDestroy(g); return fail(MC_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e)); }
+    if (e2 != hipSuccess) return fail(MC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(&nt->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { nt->graph_exec = nullptr; return fail(MC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)); }
+    nt->graph_k = nt->graph_chunk;
+    return MC_OK;
+}
+
+int run_graph(mc_net *nt, int64_t steps)
+{
+    int rc = ensure_graph(nt);
+    if (rc) return rc;
+    const mc::DevNet d = dev_view(nt);
+    while (steps > 0) {
+        const int64_t seg = std::min(steps, kSegSteps);
+        const int64_t chunks = seg / nt->graph_chunk;
+        const int rem = static_cast<int>(seg % nt->graph_chunk);
+        if (nt->timing) HIP_TRY(hipEventRecord(nt->ev0, nt->stream));
+        for (int64_t c = 0; c < chunks; ++c) HIP_TRY(hipGraphLaunch(nt->graph_exec, nt->stream));
+        for (int s = 0; s < rem; ++s) {
+            HIP_TRY(mc::launch_neuron(d, nt->block, s, nt->stream));
+            HIP_TRY(mc::launch_deliver(d, nt->deliver_grid, s, nt->stream));
+        }
+        if (rem) HIP_TRY(mc::launch_advance(d, rem, nt->stream));
+        if (nt->timing) {
+            HIP_TRY(hipEventRecord(nt->ev1, nt->stream));
+            HIP_TRY(hipEventSynchronize(nt->ev1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, nt->ev0, nt->ev1));
+            nt->kernel_ms += ms;
+            nt->launches += seg;
+        }
+        if ((rc = drain(nt))) return rc;
+        nt->step += seg;
+        steps -= seg;
+    }
+    return MC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *mc_last_error(void) { return g_err.c_str(); }
+
+int mc_config_default(mc_config *cfg)
+{
+    if (!cfg) return fail(MC_ERR_ARG, "cfg must not be NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->struct_size = sizeof(mc_config);
+    cfg->conn_probs = nullptr;
+    cfg->wfmt = MC_W_FP32;
+    cfg->poisson_on = 1;
+    cfg->init_mode = 0;
+    cfg->engine = MC_ENGINE_AUTO;
+    cfg->record_capacity = 0;
+    const double full[MC_NPOP] = {20683, 5834, 21915, 5479, 4850, 1065, 14395, 2948};
+    const double kext[MC_NPOP] = {1600, 1500, 2100, 1900, 2000, 1900, 2900, 2100};
+    for (int a = 0; a < MC_NPOP; ++a) {
+        cfg->full_size[a] = full[a];
+        cfg->k_ext[a] = kext[a];
+        cfg->i_dc_pa[a] = 0.0;
+    }
+    cfg->nu_bg_hz = 8.0;
+    cfg->dt_ms = 0.1;
+    cfg->tau_m_ms = 10.0;
+    cfg->c_m_pf = 250.0;
+    cfg->tau_syn_ms = 0.5;
+    cfg->t_ref_ms = 2.0;
+    cfg->theta_mv = 15.0;
+    cfg->w_mean_pa = 87.8;
+    cfg->w_sd_pa = 8.78;
+    cfg->g = -4.0;
+    cfg->l4e_l23e_factor = 2.0;
+    cfg->w_ext_pa = 87.8;
+    cfg->d_mean_exc_ms = 1.5;
+    cfg->d_sd_exc_ms = 0.75;
+    cfg->d_mean_inh_ms = 0.8;
+    cfg->d_sd_inh_ms = 0.4;
+    return MC_OK;
+}
+
+int mc_build_network(uint64_t seed, double scale, const mc_config *cfg, mc_net **out)
+{
+    return build_common(&seed, &scale, 1, cfg, out);
+}
+
+int mc_build_batch(const uint64_t *seeds, const double *scales, int32_t n, const mc_config *cfg, mc_net **out)
+{
+    return build_common(seeds, scales, n, cfg, out);
+}
+
+int mc_run(mc_net *net, int64_t steps)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (steps < 0) return fail(MC_ERR_ARG, "steps must be >= 0");
+    if (steps == 0) return MC_OK;
+    if (net->step + steps >= (int64_t{1} << 31)) return fail(MC_ERR_ARG, "step index would exceed 2^31");
+    int rc = run_graph(net, steps);
+    if (rc) return rc;
+    if (net->overflow) {
+        net->overflow = false;
+        return fail(MC_ERR_RECORD_OVERFLOW, "spike recorder overflowed; increase record_capacity");
+    }
+    return MC_OK;
+}
+
+int mc_get_spikes(mc_net *net, int32_t instance, int64_t *steps_out, int32_t *ids_out, int64_t cap, int64_t *count_out)
+{
+    if (!net || !count_out) return fail(MC_ERR_ARG, "net and count_out must not be NULL");
+    if (instance < 0 || instance >= net->host.n_inst) return fail(MC_ERR_ARG, "instance out of range");
+    auto &v = net->unread[instance];
+    *count_out = static_cast<int64_t>(v.size());
+    if (cap < static_cast<int64_t>(v.size())) return fail(MC_ERR_BUFFER_TOO_SMALL, "buffer too small");
+    if (!v.empty() && (!steps_out || !ids_out)) return fail(MC_ERR_ARG, "output buffers must not be NULL");
+    std::sort(v.begin(), v.end());
+    for (size_t q = 0; q < v.size(); ++q) {
+        steps_out[q] = v[q].first;
+        ids_out[q] = v[q].second;
+    }
+    v.clear();
+    return MC_OK;
+}
+
+int mc_instance_size(mc_net *net, int32_t instance, int64_t *n_neurons, int64_t *n_synapses)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (instance < 0 || instance >= net->host.n_inst) return fail(MC_ERR_ARG, "instance out of range");
+    if (n_neurons) *n_neurons = net->host.inst_off[instance + 1] - net->host.inst_off[instance];
+    if (n_synapses) *n_synapses = net->host.inst_syn_off[instance + 1] - net->host.inst_syn_off[instance];
+    return MC_OK;
+}
+
+int mc_get_state(mc_net *net, int32_t instance, float *u_mv, float *i_pa, int32_t *refr, int64_t n)
+{
+    int64_t nn = 0;
+    int rc = mc_instance_size(net, instance, &nn, nullptr);
+    if (rc) return rc;
+    if (n != nn) return fail(MC_ERR_ARG, "n must equal the instance's neuron count");
+    const int64_t o = net->host.inst_off[instance];
+    if (u_mv) HIP_TRY(hipMemcpy(u_mv, net->u + o, n * sizeof(float), hipMemcpyDeviceToHost));
+    if (i_pa) HIP_TRY(hipMemcpy(i_pa, net->cur + o, n * sizeof(float), hipMemcpyDeviceToHost));
+    if (refr) {
+        std::vector<uint8_t> r(static_cast<size_t>(n));
+        HIP_TRY(hipMemcpy(r.data(), net->refr + o, n, hipMemcpyDeviceToHost));
+        for (int64_t q = 0; q < n; ++q) refr[q] = r[q];
+    }
+    return MC_OK;
+}
+
+int mc_set_state(mc_net *net, int32_t instance, const float *u_mv, const float *i_pa, const int32_t *refr, int64_t n)
+{
+    int64_t nn = 0;
+    int rc = mc_instance_size(net, instance, &nn, nullptr);
+    if (rc) return rc;
+    if (n != nn) return fail(MC_ERR_ARG, "n must equal the instance's neuron count");
+    const int64_t o = net->host.inst_off[instance];
+    if (u_mv) HIP_TRY(hipMemcpy(net->u + o, u_mv, n * sizeof(float), hipMemcpyHostToDevice));
+    if (i_pa) HIP_TRY(hipMemcpy(net->cur + o, i_pa, n * sizeof(float), hipMemcpyHostToDevice));
+    if (refr) {
+        std::vector<uint8_t> r(static_cast<size_t>(n));
+        for (int64_t q = 0; q < n; ++q) {
+            if (refr[q] < 0 || refr[q] > 255) return fail(MC_ERR_ARG, "refractory count out of range");
+            r[q] = static_cast<uint8_t>(refr[q]);
+        }
+        HIP_TRY(hipMemcpy(net->refr + o, r.data(), n, hipMemcpyHostToDevice));
+    }
+    return MC_OK;
+}
+
+int mc_get_counters(mc_net *net, int32_t instance, mc_counters *out)
+{
+    if (!net || !out) return fail(MC_ERR_ARG, "net and out must not be NULL");
+    if (instance < -1 || instance >= net->host.n_inst) return fail(MC_ERR_ARG, "instance out of range");
+    std::vector<unsigned long long> acc(static_cast<size_t>(net->pois_slots));
+    HIP_TRY(hipMemcpy(acc.data(), net->pois_acc, acc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    mc::StepCtl c{};
+    HIP_TRY(hipMemcpy(&c, net->ctl, sizeof(c), hipMemcpyDeviceToHost));
+    out->steps = net->step;
+    out->spikes = 0;
+    out->events = 0;
+    for (int j = 0; j < net->host.n_inst; ++j)
+        if (instance < 0 || instance == j) {
+            out->spikes += net->inst_spikes[j];
+            out->events += net->inst_events[j];
+        }
+    int64_t pe = 0;
+    for (auto v : acc) pe += static_cast<int64_t>(v);
+    out->poisson_events = pe;
+    out->max_spikes_per_step = c.max_s;
+    return MC_OK;
+}
+
+int mc_get_info(mc_net *net, mc_info *out)
+{
+    if (!net || !out) return fail(MC_ERR_ARG, "net and out must not be NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->n_instances = net->host.n_inst;
+    out->ring_depth = net->host.ring;
+    out->engine = net->engine;
+    out->wfmt = net->params.wfmt;
+    out->n_neurons = net->host.n;
+    out->n_synapses = net->host.m;
+    out->graph_chunk = net->graph_chunk;
+    out->seg = net->seg;
+    out->block = net->block;
+    out->deliver_grid = net->deliver_grid;
+    return MC_OK;
+}
+
+int mc_get_csr(mc_net *net, int32_t instance, int64_t *row_ptr, int32_t *post, int32_t *wq, uint8_t *d, int64_t n_synapses)
+{
+    int64_t nn = 0, mm = 0;
+    int rc = mc_instance_size(net, instance, &nn, &mm);
+    if (rc) return rc;
+    if (n_synapses != mm) return fail(MC_ERR_ARG, "n_synapses must equal the instance's synapse count");
+    const int64_t o = net->host.inst_off[instance];
+    const int64_t so = net->host.inst_syn_off[instance];
+    if (row_ptr) {
+        std::vector<uint64_t> rp(static_cast<size_t>(nn + 1));
+        HIP_TRY(hipMemcpy(rp.data(), net->row_ptr + o, (nn + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        for (int64_t q = 0; q <= nn; ++q) row_ptr[q] = static_cast<int64_t>(rp[q]) - so;
+    }
+    if (post) {
+        HIP_TRY(hipMemcpy(post, net->tgt + so, mm * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t q = 0; q < mm; ++q) post[q] -= static_cast<int32_t>(o);
+    }
+    if (d) HIP_TRY(hipMemcpy(d, net->dly + so, mm, hipMemcpyDeviceToHost));
+    if (wq) {
+        if (net->params.wfmt == mc::kWFp32) {
+            std::vector<float> f(static_cast<size_t>(mm));
+            HIP_TRY(hipMemcpy(f.data(), static_cast<float *>(net->w) + so, mm * sizeof(float), hipMemcpyDeviceToHost));
+            for (int64_t q = 0; q < mm; ++q) wq[q] = static_cast<int32_t>(std::nearbyint(static_cast<double>(f[q]) * 256.0));
+        } else {
+            std::vector<uint16_t> h(static_cast<size_t>(mm));
+            HIP_TRY(hipMemcpy(h.data(), static_cast<uint16_t *>(net->w) + so, mm * sizeof(uint16_t), hipMemcpyDeviceToHost));
+            for (int64_t q = 0; q < mm; ++q) {
+                const double v = net->params.wfmt == mc::kWFp16 ? mc::half_value(h[q]) : mc::bf16_value(h[q]);
+                wq[q] = static_cast<int32_t>(std::nearbyint(v * 256.0));
+            }
+        }
+    }
+    return MC_OK;
+}
+
+int mc_set_launch(mc_net *net, const mc_launch *l)
+{
+    if (!net || !l) return fail(MC_ERR_ARG, "net and l must not be NULL");
+    if (l->engine == MC_ENGINE_TILED) return fail(MC_ERR_UNSUPPORTED, "tiled engine not available");
+    if (l->graph_chunk && (l->graph_chunk < 1 || l->graph_chunk > 1024)) return fail(MC_ERR_ARG, "graph_chunk must be in [1, 1024]");
+    if (l->seg && l->seg != 64 && l->seg != 128 && l->seg != 256 && l->seg != 512) return fail(MC_ERR_ARG, "seg must be 64, 128, 256 or 512");
+    if (l->block && l->block != 64 && l->block != 128 && l->block != 256 && l->block != 512) return fail(MC_ERR_ARG, "block must be 64, 128, 256 or 512");
+    if (l->deliver_grid < 0) return fail(MC_ERR_ARG, "deliver_grid must be >= 1");
+    bool changed = false;
+    auto set = [&changed](int &dst, int v) { if (v && dst != v) { dst = v; changed = true; } };
+    set(net->graph_chunk, l->graph_chunk);
+    set(net->seg, l->seg);
+    set(net->block, l->block);
+    set(net->deliver_grid, l->deliver_grid);
+    if (changed && net->graph_exec) {
+        hipGraphExecDestroy(net->graph_exec);
+        net->graph_exec = nullptr;
+        net->graph_k = 0;
+    }
+    return MC_OK;
+}
+
+int mc_set_stream(mc_net *net, void *hip_stream)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    if (net->own_stream) HIP_TRY(hipStreamDestroy(net->stream));
+    if (hip_stream) {
+        net->stream = static_cast<hipStream_t>(hip_stream);
+        net->own_stream = false;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking));
+        net->own_stream = true;
+    }
+    return MC_OK;
+}
+
+int mc_set_timing(mc_net *net, int32_t on)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    net->timing = on != 0;
+    net->kernel_ms = 0.0;
+    net->launches = 0;
+    return MC_OK;
+}
+
+int mc_get_timing(mc_net *net, double *kernel_ms, int64_t *launches)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (kernel_ms) *kernel_ms = net->kernel_ms;
+    if (launches) *launches = net->launches;
+    return MC_OK;
+}
+
+int mc_tune(mc_net *net, int64_t trial_steps)
+{
+    (void)trial_steps;
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    return fail(MC_ERR_UNSUPPORTED, "autotuner not available");
+}
+
+int mc_save_state(mc_net *net, const char *path)
+{
+    (void)path;
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    return fail(MC_ERR_UNSUPPORTED, "checkpointing not available");
+}
+
+int mc_load_state(mc_net *net, const char *path)
+{
+    (void)path;
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    return fail(MC_ERR_UNSUPPORTED, "checkpointing not available");
+}
+
+void mc_free(mc_net *net) { release(net); }
+
+}  // extern "C"

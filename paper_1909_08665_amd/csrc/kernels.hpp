@@ -1,0 +1,82 @@
+// kernels.hpp -- device-side view of a network and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mc {
+
+constexpr int kPoisMaxDev = 24;
+constexpr uint64_t kMask40 = (uint64_t{1} << 40) - 1;
+constexpr uint32_t kFlagRecordOverflow = 1u;
+
+// Control words of the step loop, in device memory.
+struct StepCtl {
+    int64_t nbase;                    // step index at the start of the current launch chunk
+    int64_t rec_total;                // spikes recorded since the last drain
+    unsigned long long cnt[3];        // per step (n % 3): spikes << 40 | delivery work items
+    unsigned long long events;        // recurrent synaptic events
+    int32_t max_s;                    // largest spike count of one step
+    uint32_t flags;
+};
+
+// Everything a kernel needs, passed by value.
+struct DevNet {
+    int32_t n;                        // neurons (all instances)
+    int32_t ring_mask;                // R - 1, R a power of two
+    int32_t ref_steps;
+    int32_t wq_ext;
+    float p22, p11, p21, theta;
+    int32_t poisson_on;
+    int32_t seg;                      // synapses per delivery work item
+    int32_t wfmt;
+    int32_t pad0;
+    // neuron state and description
+    float *u;
+    float *cur;                       // synaptic current I
+    uint8_t *refr;
+    const uint32_t *meta;             // (instance << 3) | population
+    const int32_t *inst_off;          // [instances + 1]
+    const uint64_t *seeds;            // [instances]
+    const float *cdc;                 // [8] P20 * I_dc
+    const uint64_t *pois_thr;         // [8 * 24]
+    int32_t *ring;                    // [R][n]
+    // synapse store, CSR by presynaptic neuron
+    const uint64_t *row_ptr;          // [n + 1]
+    const int32_t *tgt;               // [m] global target id
+    const void *w;                    // [m] float, or 16-bit FP16/BF16 bits
+    const uint8_t *dly;               // [m] delay in steps
+    // step loop
+    StepCtl *ctl;
+    uint64_t *work;                   // delivery work items: pre << 32 | chunk
+    unsigned long long *pois_acc;     // per-block Poisson event sums
+    int32_t *rec_id;
+    int32_t *rec_step;
+    int64_t rec_cap;
+};
+
+// Tiled persistent engine: neurons cut into tiles of `tile` neurons, one
+// workgroup per tile, input ring of the tile resident in LDS.
+struct TiledNet {
+    DevNet base;
+    int32_t tile;                     // neurons per tile
+    int32_t n_tiles;
+    const uint32_t *sub_ptr;          // [n * n_tiles + 1] start of the sub-row of (pre, tile)
+    const uint16_t *ltgt;             // [m] target id local to its tile
+    int32_t *tile_cnt;                // [2][n_tiles] spikes published per tile (step parity)
+    int32_t *tile_spk;                // [2][n] spike ids published per tile (tile-major slots)
+    uint32_t *bar;                    // grid barrier arrival counter
+    int32_t *state_ring;              // [n_tiles][R][tile] ring saved between launches
+};
+
+hipError_t launch_neuron(const DevNet &d, int block, int s_off, hipStream_t st);
+hipError_t launch_deliver(const DevNet &d, int grid, int s_off, hipStream_t st);
+hipError_t launch_advance(const DevNet &d, int steps, hipStream_t st);
+hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st);
+
+// Tiled engine: one cooperative launch advances `steps` steps.
+hipError_t launch_tiled(const TiledNet &t, int64_t steps, int threads, hipStream_t st);
+int tiled_threads_for(int tile);
+size_t tiled_lds_bytes(int tile, int ring);
+
+}  // namespace mc
