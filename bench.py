@@ -1,0 +1,207 @@
+"""Benchmark: real-time factor and synaptic events/s of the full-scale cortical
+microcircuit (77,169 neurons, ~3e8 synapses, dt = 0.1 ms) on one MI355X.
+
+One benchmark "step" is one simulation step: Poisson drive, LIF update, spike
+compaction and delivery of every spike's synaptic row, for the whole network.
+Prints one JSON line.  Inputs are synthetic and seeded; the network is built and
+uploaded before the timed region (the synapse store is resident in HBM).
+
+    python bench.py [--gpus 1] [--steps 100000] [--warmup 1000]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DT_S = 1e-4
+HBM_PEAK_GBS = 8000.0
+METRIC = "real-time factor + synaptic events/s, full 77k-neuron microcircuit, 1 GPU"
+WFMT = {"fp32": 0, "fp16": 1, "bf16": 2}
+BYTES_PER_EVENT = {"fp32": 9, "fp16": 7, "bf16": 7}     # target int32 + weight + delay u8
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seed, scale, conn, warm, steps):
+    """The oracle (FP32 mirror) on this host's cores, on a bounded sample of the
+    same workload: same network, `steps` steps after `warm` untimed steps."""
+    from oracle import oracle as O
+
+    cores = O.max_threads()
+    t = time.time()
+    net = O.OracleNet.build(seed, scale, conn.reshape(64))
+    log(f"oracle build {time.time() - t:.1f}s ({cores} threads)")
+    net.run(warm)
+    net.spikes(clear=True)
+    c0 = net.counters()
+    t0 = time.perf_counter()
+    net.run(steps)
+    wall = time.perf_counter() - t0
+    c1 = net.counters()
+    ev = c1["events"] - c0["events"]
+    log(f"oracle {steps} steps in {wall:.2f}s")
+    return {"value": round(steps * DT_S / wall, 6), "unit": "x real time (simulated s per wall s)",
+            "events_per_s": round(ev / wall, 1), "cores": cores, "kind": "oracle",
+            "sample": f"FP32-mirror oracle, same seeded network (scale {scale}), steps {warm}..{warm + steps} "
+                      f"({steps * DT_S:.2f} s biological time), build excluded"}
+
+
+PHASES = (("update+publish", 0, 1), ("next Poisson", 1, 3), ("wait for all tiles", 3, 4),
+          ("spike ids + sub-row pointers", 4, 5), ("delivery", 5, 6))
+
+
+def step_latency(net):
+    """Per-step timing of the tiled kernel from its 100 MHz phase timestamps:
+    phase means and the step period against the 100 us real-time deadline."""
+    tr = net.trace().astype(np.int64)                 # [steps, tiles, 8]
+    if tr.shape[0] < 2:
+        return None
+    tr[:, :, 5] = np.where(tr[:, :, 5] == 0, tr[:, :, 4], tr[:, :, 5])   # steps without spikes
+    per = np.diff(tr[:, :, 0], axis=0).max(axis=1) * 0.01                # us, slowest tile
+    phases = {}
+    for name, a, b in PHASES:
+        d = (tr[:, :, b] - tr[:, :, a]) * 0.01
+        phases[name] = round(float(d.mean()), 3)
+        log(f"  phase {name:30s} mean {d.mean():7.3f} us  p99 {np.percentile(d, 99):7.3f} us")
+    log(f"  step period mean {per.mean():.3f} us, p50 {np.median(per):.3f}, p99 {np.percentile(per, 99):.3f}, "
+        f"max {per.max():.3f}")
+    return {"steps": int(tr.shape[0] - 1), "mean_us": round(float(per.mean()), 3),
+            "p50_us": round(float(np.median(per)), 3), "p99_us": round(float(np.percentile(per, 99)), 3),
+            "max_us": round(float(per.max()), 3), "deadline_us": 100.0,
+            "frac_over_deadline": float((per > 100.0).mean()), "phases_us": phases}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--wfmt", choices=sorted(WFMT), default="fp32")
+    ap.add_argument("--engine", choices=["auto", "graph", "tiled"], default="auto")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-warm", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=5000)
+    ap.add_argument("--trace", type=int, default=0,
+                    help="record per-step phase timestamps for the first K timed steps (tiled engine)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(independent instances would shard across GPUs with no exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1909_08665_amd as mc
+    from synth_inputs import standin_conn_table, standin_description
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    conn = standin_conn_table()
+    engine = {"auto": mc.ENGINE_AUTO, "graph": mc.ENGINE_GRAPH, "tiled": mc.ENGINE_TILED}[args.engine]
+
+    t = time.time()
+    net = mc.Network.build(args.seed, args.scale, conn, wfmt=WFMT[args.wfmt], engine=engine)
+    if args.tile:
+        net.set_launch(engine=mc.ENGINE_TILED, tile=args.tile)
+    n_neurons, n_syn = net.size()
+    log(f"build+upload {time.time() - t:.1f}s: {n_neurons} neurons, {n_syn} synapses")
+    if args.tune:
+        net.tune(500)
+    info = net.info()
+    log("launch", {k: info[k] for k in ("engine", "tile_neurons", "n_tiles", "ring_depth", "graph_chunk", "seg")})
+
+    net.run(args.warmup)
+    net.spikes()
+    if args.trace and info["engine"] == mc.ENGINE_TILED:
+        net.set_trace(args.trace)
+    c0 = net.counters()
+    net.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches = net.timing()
+    c1 = net.counters()
+    st, _ = net.spikes()
+    events = c1["events"] - c0["events"]
+    spikes = c1["spikes"] - c0["spikes"]
+    rtf = args.steps * DT_S / wall
+    log(f"{args.steps} steps in {wall:.3f}s: RTF {rtf:.2f}, {events / wall:.3e} events/s, "
+        f"{spikes / args.steps:.1f} spikes/step")
+
+    # Roofline of the dominant kernel: algorithmic HBM bytes it must move
+    # (synapse words of every delivered event, plus the per-spike row pointers:
+    # one (row, tile) pointer pair per tile for the tiled engine, one row pointer
+    # pair for the graph engine, plus the per-neuron state traffic of the graph
+    # engine's HBM-resident state) over its HIP-event-timed duration.
+    tiled = info["engine"] == mc.ENGINE_TILED
+    b_event = BYTES_PER_EVENT[args.wfmt]
+    if tiled:
+        per_spike = 4 * (info["n_tiles"] + 1)
+        per_neuron_step = 0
+        kname = "k_tiled (persistent step kernel)"
+    else:
+        per_spike = 16
+        per_neuron_step = 26
+        kname = "k_neuron + k_deliver (graph-captured step)"
+    algo_bytes = events * b_event + spikes * per_spike + args.steps * n_neurons * per_neuron_step
+    avg_launch_ms = kernel_ms / max(1, launches)
+    achieved = algo_bytes / max(1, launches) / (avg_launch_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None, "kernel": kname,
+                "launches": launches, "avg_launch_ms": round(avg_launch_ms, 4),
+                "bytes_per_launch": int(algo_bytes / max(1, launches))}
+
+    latency = step_latency(net) if args.trace and tiled else None
+
+    out = {
+        "metric": METRIC,
+        "value": round(rtf, 4),
+        "unit": "x real time (simulated s per wall s)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"microcircuit scale {args.scale} ({n_neurons} neurons, {n_syn} synapses), "
+                               f"{args.wfmt.upper()} weight store, {args.steps * DT_S:g} s biological time, "
+                               f"Poisson background, dt 0.1 ms",
+                   "seed": args.seed, "conn_table": standin_description(),
+                   "engine": "tiled" if tiled else "graph", "tile": info["tile_neurons"],
+                   "n_tiles": info["n_tiles"], "ring_depth": info["ring_depth"]},
+        "events_per_s": round(events / wall, 1),
+        "spikes_per_step": round(spikes / args.steps, 3),
+        "max_spikes_per_step": c1["max_spikes_per_step"],
+        "context": {"paper_spinnaker_rtf": 1.0, "paper_spinnaker_events_per_s": 9.343e8},
+        "roofline": roofline,
+    }
+    if latency:
+        out["step_latency"] = latency
+    net.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.seed, args.scale, conn, args.cpu_warm, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -125,6 +125,7 @@ typedef struct mc_info {
 /* Launch knobs chosen by the autotuner or set by hand (0 = keep current). */
 typedef struct mc_launch {
     int32_t engine;
+    int32_t tile;                /* TILED engine: neurons per tile, 64..1024 */
     int32_t graph_chunk;         /* 1..1024 */
     int32_t seg;                 /* 64, 128, 256 or 512 */
     int32_t block;               /* 64, 128, 256 or 512 */
@@ -205,7 +206,8 @@ int mc_get_csr(struct mc_net *net, int32_t instance, int64_t *row_ptr, int32_t *
 /* Number of neurons and synapses of `instance`. */
 int mc_instance_size(struct mc_net *net, int32_t instance, int64_t *n_neurons, int64_t *n_synapses);
 
-/* Select launch knobs (engine, graph chunk, work-item size, block, grid). */
+/* Select launch knobs (engine, tile size, graph chunk, work-item size, block, grid).
+   MC_ERR_UNSUPPORTED if the TILED engine cannot hold the network (LDS, co-residency). */
 int mc_set_launch(struct mc_net *net, const mc_launch *l);
 
 /*
@@ -225,6 +227,19 @@ int mc_set_stream(struct mc_net *net, void *hip_stream);
  */
 int mc_set_timing(struct mc_net *net, int32_t on);
 int mc_get_timing(struct mc_net *net, double *kernel_ms, int64_t *launches);
+
+/*
+ * Per-step latency record of the TILED engine (the paper's true-real-time
+ * criterion, Sec. 2c and 3a(iii): every step must finish within its period).
+ * mc_set_trace(net, k) records, for the first k steps of the next mc_run, eight
+ * words per (step, tile) from the GPU's constant 100 MHz clock: step start,
+ * spikes published, barrier arrival, next Poisson draw done, barrier passed,
+ * spike counts gathered, delivery done, and the step's spike count.  k = 0
+ * disables it.  mc_get_trace copies [k][n_tiles][8] words into `out` (cap
+ * entries) and sets *count; MC_ERR_BUFFER_TOO_SMALL if cap is too small.
+ */
+int mc_set_trace(struct mc_net *net, int32_t steps);
+int mc_get_trace(struct mc_net *net, uint64_t *out, int64_t cap, int64_t *count);
 
 /*
  * Checkpoint: write / read the full dynamic state (step counter, neuron state,

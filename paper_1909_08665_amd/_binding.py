@@ -53,7 +53,7 @@ class McInfo(C.Structure):
 
 
 class McLaunch(C.Structure):
-    _fields_ = [("engine", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
+    _fields_ = [("engine", C.c_int32), ("tile", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
                 ("deliver_grid", C.c_int32)]
 
 
@@ -61,7 +61,8 @@ class McLaunch(C.Structure):
 EXPORTS = ("mc_config_default", "mc_build_network", "mc_build_batch", "mc_run", "mc_get_spikes",
            "mc_get_state", "mc_set_state", "mc_get_counters", "mc_get_info", "mc_get_csr",
            "mc_instance_size", "mc_set_launch", "mc_tune", "mc_set_stream", "mc_set_timing",
-           "mc_get_timing", "mc_save_state", "mc_load_state", "mc_free", "mc_last_error")
+           "mc_get_timing", "mc_set_trace", "mc_get_trace", "mc_save_state", "mc_load_state", "mc_free",
+           "mc_last_error")
 
 _lib = None
 
@@ -101,6 +102,8 @@ def lib():
     L.mc_set_stream.argtypes = [P, P]
     L.mc_set_timing.argtypes = [P, I32]
     L.mc_get_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I64)]
+    L.mc_set_trace.argtypes = [P, I32]
+    L.mc_get_trace.argtypes = [P, P, I64, C.POINTER(I64)]
     L.mc_save_state.argtypes = [P, C.c_char_p]
     L.mc_load_state.argtypes = [P, C.c_char_p]
     L.mc_free.argtypes = [P]
@@ -184,8 +187,8 @@ class Network:
     def run(self, steps):
         _check(lib().mc_run(self._h, int(steps)))
 
-    def set_launch(self, engine=0, graph_chunk=0, seg=0, block=0, deliver_grid=0):
-        l = McLaunch(engine, graph_chunk, seg, block, deliver_grid)
+    def set_launch(self, engine=0, tile=0, graph_chunk=0, seg=0, block=0, deliver_grid=0):
+        l = McLaunch(engine, tile, graph_chunk, seg, block, deliver_grid)
         _check(lib().mc_set_launch(self._h, C.byref(l)))
 
     def tune(self, trial_steps=200):
@@ -203,6 +206,21 @@ class Network:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().mc_get_timing(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_trace(self, steps):
+        """Record per-step phase timestamps for the first `steps` steps of the next run."""
+        _check(lib().mc_set_trace(self._h, int(steps)))
+
+    def trace(self):
+        """[steps, tiles, 8] uint64: 100 MHz timestamps of the step phases (slot 7:
+        the step's spike count)."""
+        cnt = C.c_int64()
+        lib().mc_get_trace(self._h, None, 0, C.byref(cnt))
+        out = np.zeros(cnt.value, dtype=np.uint64)
+        if cnt.value:
+            _check(lib().mc_get_trace(self._h, _ptr(out), cnt.value, C.byref(cnt)))
+        info = self.info()
+        return out.reshape(-1, max(1, info["n_tiles"]), 8)
 
     def save(self, path):
         _check(lib().mc_save_state(self._h, os.fsencode(path)))

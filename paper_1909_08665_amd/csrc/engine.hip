@@ -3,13 +3,18 @@
 // The GRAPH engine captures K steps (neuron kernel + delivery kernel per step,
 // then a one-thread counter advance) in a hipGraph and replays it; the step
 // index lives in device memory, so the spike count never returns to the host
-// inside a run.  The host drains the spike recorder every `kSegSteps` steps.
+// inside a run.  The TILED engine advances a whole segment of steps in one
+// cooperative persistent launch.  Both keep the dynamic state (u, I, refractory
+// counts, the [R][N] ring, step index) in the same global arrays between
+// launches, so engines can be switched between runs.  The host drains the spike
+// recorder between segments, sized so the recorder stays at most a quarter full.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <utility>
 #include <vector>
@@ -35,7 +40,7 @@ int fail(int code, const std::string &msg)
             return fail(MC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
     } while (0)
 
-constexpr int64_t kSegSteps = 1000;   // steps between recorder drains
+constexpr int64_t kSegMin = 100, kSegMax = 10000;   // steps between recorder drains
 
 }  // namespace
 
@@ -72,7 +77,19 @@ struct mc_net {
     int32_t *h_rec_id = nullptr, *h_rec_step = nullptr;
     mc::StepCtl *h_ctl = nullptr;
 
+    // tiled engine
+    int tile = 0, n_tiles = 0, tiled_threads = 0;
+    uint32_t *sub_ptr = nullptr;
+    uint64_t *xchg = nullptr, *xent = nullptr;
+    uint32_t *abort_flag = nullptr;
+    uint64_t *trace = nullptr;
+    int32_t trace_steps = 0;
+    int32_t trace_tiles = 0;
+    int n_cu = 0;
+    size_t lds_limit = 0;
+
     // launch configuration
+    int64_t seg_steps = 1000;
     int engine = MC_ENGINE_GRAPH;
     int graph_chunk = 50;
     int seg = 256;
@@ -148,7 +165,7 @@ void release(mc_net *nt)
     if (nt->graph_exec) hipGraphExecDestroy(nt->graph_exec);
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
-                    nt->rec_id, nt->rec_step};
+                    nt->rec_id, nt->rec_step, nt->sub_ptr, nt->xchg, nt->xent, nt->abort_flag, nt->trace};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (nt->h_rec_id) hipHostFree(nt->h_rec_id);
@@ -204,6 +221,12 @@ int upload(mc_net *nt, const mc_config *cfg)
     const int64_t N = H.n, M = H.m;
     int rc;
     HIP_TRY(hipGetDevice(&nt->device));
+    {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, nt->device));
+        nt->n_cu = prop.multiProcessorCount;
+        nt->lds_limit = prop.sharedMemPerBlock;
+    }
     HIP_TRY(hipStreamCreateWithFlags(&nt->stream, hipStreamNonBlocking));
     nt->own_stream = true;
     HIP_TRY(hipEventCreate(&nt->ev0));
@@ -267,6 +290,55 @@ int upload(mc_net *nt, const mc_config *cfg)
     return MC_OK;
 }
 
+// Neurons per tile: one workgroup per compute unit when that fits, at least 64.
+int default_tile(const mc_net *nt)
+{
+    const int64_t N = nt->host.n;
+    const int cus = nt->n_cu > 0 ? nt->n_cu : 256;
+    int64_t tile = (N + cus - 1) / cus;
+    tile = std::max<int64_t>(64, tile);
+    return static_cast<int>(std::min<int64_t>(tile, 1024));
+}
+
+// Prepare the tiled engine for `tile` neurons per workgroup: check that the LDS
+// ring fits and that every workgroup can be resident at once, then build the
+// per-(row, tile) sub-row pointers on the device.
+int setup_tiled(mc_net *nt, int tile)
+{
+    const int64_t N = nt->host.n;
+    if (tile < 64 || tile > 1024) return fail(MC_ERR_ARG, "tile must be in [64, 1024]");
+    if (nt->host.m >= (int64_t{1} << 32)) return fail(MC_ERR_UNSUPPORTED, "tiled engine needs fewer than 2^32 synapses");
+    const int T = static_cast<int>((N + tile - 1) / tile);
+    const int threads = mc::tiled_threads_for(tile);
+    const size_t lds = mc::tiled_lds_bytes(tile, nt->host.ring, T);
+    const size_t lds_static = 8 * mc::kPoisMaxDev * sizeof(uint64_t) + 32 * sizeof(int);
+    if (lds + lds_static > 160 * 1024) return fail(MC_ERR_UNSUPPORTED, "tile ring does not fit in LDS");
+    int per_cu = 0;
+    HIP_TRY(mc::tiled_max_coresident(nt->params.wfmt, threads, lds, &per_cu));
+    if (static_cast<int64_t>(per_cu) * nt->n_cu < T)
+        return fail(MC_ERR_UNSUPPORTED, "tiles cannot all be resident at once (" + std::to_string(T) + " tiles)");
+    if (nt->tile == tile && nt->sub_ptr) return MC_OK;
+    for (void *b : {static_cast<void *>(nt->sub_ptr), static_cast<void *>(nt->xchg), static_cast<void *>(nt->xent),
+                    static_cast<void *>(nt->abort_flag)})
+        if (b) hipFree(b);
+    nt->sub_ptr = nullptr;
+    nt->xchg = nullptr;
+    nt->xent = nullptr;
+    nt->abort_flag = nullptr;
+    nt->tile = 0;
+    int rc;
+    if ((rc = dalloc(&nt->sub_ptr, static_cast<size_t>(N) * T + 1)) || (rc = dalloc(&nt->xchg, 2 * T)) ||
+        (rc = dalloc(&nt->xent, static_cast<size_t>(2) * T * tile)) || (rc = dalloc(&nt->abort_flag, 1)))
+        return rc;
+    HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * T * tile * sizeof(uint64_t), nt->stream));
+    HIP_TRY(mc::launch_subrow_ptr(dev_view(nt), tile, T, nt->sub_ptr, static_cast<uint64_t>(nt->host.m), nt->stream));
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    nt->tile = tile;
+    nt->n_tiles = T;
+    nt->tiled_threads = threads;
+    return MC_OK;
+}
+
 int build_common(const uint64_t *seeds, const double *scales, int32_t n, const mc_config *cfg, mc_net **out)
 {
     if (!out) return fail(MC_ERR_ARG, "out must not be NULL");
@@ -298,8 +370,18 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
     nt->unread.assign(n, {});
     nt->inst_spikes.assign(n, 0);
     nt->inst_events.assign(n, 0);
-    nt->engine = cfg->engine == MC_ENGINE_TILED ? MC_ENGINE_TILED : MC_ENGINE_GRAPH;
-    if (nt->engine == MC_ENGINE_TILED) { release(nt); return fail(MC_ERR_UNSUPPORTED, "tiled engine not available"); }
+    nt->engine = MC_ENGINE_GRAPH;
+    if (cfg->engine != MC_ENGINE_GRAPH) {
+        const int want = default_tile(nt);
+        rc = setup_tiled(nt, want);
+        if (rc == MC_OK) {
+            nt->engine = MC_ENGINE_TILED;
+        } else if (cfg->engine == MC_ENGINE_TILED) {
+            release(nt);
+            return rc;
+        }
+    }
+    g_err.clear();
     *out = nt;
     return MC_OK;
 }
@@ -335,6 +417,58 @@ int drain(mc_net *nt)
         nt->inst_events[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
     }
     if (total > nt->rec_cap || (nt->h_ctl->flags & mc::kFlagRecordOverflow)) nt->overflow = true;
+    if (nt->h_ctl->flags & mc::kFlagTimeout) return fail(MC_ERR_HIP, "a cross-tile wait timed out");
+    return MC_OK;
+}
+
+// Steps until the next drain: keep the recorder at most a quarter full at the
+// spike rate of the last segment.
+void adapt_segment(mc_net *nt, int64_t steps_done, int64_t spikes_done)
+{
+    const double per_step = steps_done > 0 ? static_cast<double>(spikes_done) / steps_done : 0.0;
+    const double fit = static_cast<double>(nt->rec_cap) / (4.0 * per_step + 64.0);
+    nt->seg_steps = std::max<int64_t>(kSegMin, std::min<int64_t>(kSegMax, static_cast<int64_t>(fit)));
+}
+
+int run_tiled(mc_net *nt, int64_t steps)
+{
+    mc::TiledNet tn{};
+    tn.base = dev_view(nt);
+    tn.tile = nt->tile;
+    tn.n_tiles = nt->n_tiles;
+    tn.sub_ptr = nt->sub_ptr;
+    tn.xchg = nt->xchg;
+    tn.xent = nt->xent;
+    tn.abort = nt->abort_flag;
+    bool first = true;
+    while (steps > 0) {
+        // the phase trace covers the first steps of the first launch of this run
+        tn.trace = first && nt->trace_tiles == nt->n_tiles ? nt->trace : nullptr;
+        tn.trace_steps = nt->trace_steps;
+        first = false;
+        const int64_t seg = std::min(steps, nt->seg_steps);
+        // Tile words from an earlier launch carry older tags; clearing them rules out
+        // a tag match across a jump of the step index (engine switch).
+        HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint64_t), nt->stream));
+        HIP_TRY(hipMemsetAsync(nt->abort_flag, 0, sizeof(uint32_t), nt->stream));
+        if (nt->timing) HIP_TRY(hipEventRecord(nt->ev0, nt->stream));
+        HIP_TRY(mc::launch_tiled(tn, seg, nt->tiled_threads, nt->stream));
+        if (nt->timing) {
+            HIP_TRY(hipEventRecord(nt->ev1, nt->stream));
+            HIP_TRY(hipEventSynchronize(nt->ev1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, nt->ev0, nt->ev1));
+            nt->kernel_ms += ms;
+            nt->launches += 1;
+        }
+        const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
+        int rc = drain(nt);
+        if (rc) return rc;
+        const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
+        adapt_segment(nt, seg, after - before);
+        nt->step += seg;
+        steps -= seg;
+    }
     return MC_OK;
 }
 
@@ -369,8 +503,11 @@ int run_graph(mc_net *nt, int64_t steps)
     int rc = ensure_graph(nt);
     if (rc) return rc;
     const mc::DevNet d = dev_view(nt);
+    // The per-step counts are only meaningful inside a graph run; another engine
+    // may have advanced the step index since, so start from clean buffers.
+    HIP_TRY(hipMemsetAsync(nt->ctl->cnt, 0, sizeof(nt->ctl->cnt), nt->stream));
     while (steps > 0) {
-        const int64_t seg = std::min(steps, kSegSteps);
+        const int64_t seg = std::min(steps, nt->seg_steps);
         const int64_t chunks = seg / nt->graph_chunk;
         const int rem = static_cast<int>(seg % nt->graph_chunk);
         if (nt->timing) HIP_TRY(hipEventRecord(nt->ev0, nt->stream));
@@ -388,7 +525,10 @@ int run_graph(mc_net *nt, int64_t steps)
             nt->kernel_ms += ms;
             nt->launches += seg;
         }
+        const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
         if ((rc = drain(nt))) return rc;
+        const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
+        adapt_segment(nt, seg, after - before);
         nt->step += seg;
         steps -= seg;
     }
@@ -457,7 +597,7 @@ int mc_run(mc_net *net, int64_t steps)
     if (steps < 0) return fail(MC_ERR_ARG, "steps must be >= 0");
     if (steps == 0) return MC_OK;
     if (net->step + steps >= (int64_t{1} << 31)) return fail(MC_ERR_ARG, "step index would exceed 2^31");
-    int rc = run_graph(net, steps);
+    int rc = net->engine == MC_ENGINE_TILED ? run_tiled(net, steps) : run_graph(net, steps);
     if (rc) return rc;
     if (net->overflow) {
         net->overflow = false;
@@ -562,6 +702,8 @@ int mc_get_info(mc_net *net, mc_info *out)
     out->wfmt = net->params.wfmt;
     out->n_neurons = net->host.n;
     out->n_synapses = net->host.m;
+    out->tile_neurons = net->engine == MC_ENGINE_TILED ? net->tile : 0;
+    out->n_tiles = net->engine == MC_ENGINE_TILED ? net->n_tiles : 0;
     out->graph_chunk = net->graph_chunk;
     out->seg = net->seg;
     out->block = net->block;
@@ -607,7 +749,8 @@ int mc_get_csr(mc_net *net, int32_t instance, int64_t *row_ptr, int32_t *post, i
 int mc_set_launch(mc_net *net, const mc_launch *l)
 {
     if (!net || !l) return fail(MC_ERR_ARG, "net and l must not be NULL");
-    if (l->engine == MC_ENGINE_TILED) return fail(MC_ERR_UNSUPPORTED, "tiled engine not available");
+    if (l->engine < 0 || l->engine > MC_ENGINE_TILED) return fail(MC_ERR_ARG, "unknown engine");
+    if (l->tile && (l->tile < 64 || l->tile > 1024)) return fail(MC_ERR_ARG, "tile must be in [64, 1024]");
     if (l->graph_chunk && (l->graph_chunk < 1 || l->graph_chunk > 1024)) return fail(MC_ERR_ARG, "graph_chunk must be in [1, 1024]");
     if (l->seg && l->seg != 64 && l->seg != 128 && l->seg != 256 && l->seg != 512) return fail(MC_ERR_ARG, "seg must be 64, 128, 256 or 512");
     if (l->block && l->block != 64 && l->block != 128 && l->block != 256 && l->block != 512) return fail(MC_ERR_ARG, "block must be 64, 128, 256 or 512");
@@ -622,6 +765,15 @@ int mc_set_launch(mc_net *net, const mc_launch *l)
         hipGraphExecDestroy(net->graph_exec);
         net->graph_exec = nullptr;
         net->graph_k = 0;
+    }
+    if (l->engine == MC_ENGINE_GRAPH) {
+        net->engine = MC_ENGINE_GRAPH;
+    } else if (l->engine == MC_ENGINE_TILED || (l->tile && net->engine == MC_ENGINE_TILED) ||
+               (l->engine == MC_ENGINE_AUTO && l->tile)) {
+        const int tile = l->tile ? l->tile : (net->tile ? net->tile : default_tile(net));
+        const int rc = setup_tiled(net, tile);
+        if (rc) return rc;
+        net->engine = MC_ENGINE_TILED;
     }
     return MC_OK;
 }
@@ -638,6 +790,36 @@ int mc_set_stream(mc_net *net, void *hip_stream)
         HIP_TRY(hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking));
         net->own_stream = true;
     }
+    return MC_OK;
+}
+
+int mc_set_trace(mc_net *net, int32_t steps)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (steps < 0 || steps > 65536) return fail(MC_ERR_ARG, "trace steps must be in [0, 65536]");
+    if (net->trace) HIP_TRY(hipFree(net->trace));
+    net->trace = nullptr;
+    net->trace_steps = 0;
+    net->trace_tiles = 0;
+    if (steps == 0) return MC_OK;
+    if (net->engine != MC_ENGINE_TILED) return fail(MC_ERR_UNSUPPORTED, "step tracing needs the TILED engine");
+    const size_t count = static_cast<size_t>(steps) * net->n_tiles * mc::kTraceSlots;
+    int rc = dalloc(&net->trace, count);
+    if (rc) return rc;
+    HIP_TRY(hipMemset(net->trace, 0, count * sizeof(uint64_t)));
+    net->trace_steps = steps;
+    net->trace_tiles = net->n_tiles;
+    return MC_OK;
+}
+
+int mc_get_trace(mc_net *net, uint64_t *out, int64_t cap, int64_t *count)
+{
+    if (!net || !count) return fail(MC_ERR_ARG, "net and count must not be NULL");
+    const int64_t n = static_cast<int64_t>(net->trace_steps) * net->trace_tiles * mc::kTraceSlots;
+    *count = n;
+    if (n == 0) return MC_OK;
+    if (!out || cap < n) return fail(MC_ERR_BUFFER_TOO_SMALL, "buffer too small");
+    HIP_TRY(hipMemcpy(out, net->trace, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
     return MC_OK;
 }
 

@@ -265,3 +265,394 @@ hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st)
 }
 
 }  // namespace mc
+
+// ===========================================================================
+// Tiled persistent engine.
+//
+// One workgroup per tile of consecutive neurons, all workgroups co-resident
+// (cooperative launch).  A workgroup keeps its tile's neuron state in registers
+// and its delay ring [R][tile] in LDS for the whole launch; the synapse rows stay
+// in HBM and each spiking row is read once, every tile reading only the sub-row
+// that targets its own neurons.  Per step:
+//   1. update the tile (slot read/clear in LDS, Poisson, LIF), compact spikes;
+//   2. publish the tile's spikes as self-tagged 64-bit words (below);
+//   3. draw the next step's Poisson counts while the other tiles publish;
+//   4. wait until every tile's word of this step is visible -- this is the
+//      step's only grid-wide synchronisation -- and gather the spike ids;
+//   5. read this tile's sub-row of every spiking row and add the weights into
+//      the LDS ring with LDS integer atomics.
+//
+// Exchange protocol: each tile owns one word per step parity,
+//     bits 63..48 tag (step n + 1, 15 bits, top bit set), 47..32 spike count,
+//     31..0 first spike id,
+// and, for its 2nd, 3rd, ... spikes, entry words (tag32 = n + 1 | spike id).
+// Words are written and polled with relaxed agent-scope atomics; a reader
+// accepts a word only when its tag matches, so no fence or counter is needed:
+// a 64-bit aligned store is seen whole or not at all.  A tile cannot publish
+// step n+2 (same parity) before it has seen every tile's step n+1 word, which
+// every tile writes only after finishing its reads of step n.
+// ===========================================================================
+namespace mc {
+namespace {
+
+constexpr int kSpkBatch = 2048;              // spikes processed per delivery batch
+constexpr uint32_t kSpinLimit = 1u << 24;    // polls before a wait gives up
+
+// Exclusive prefix sum of one value per thread, in thread order; returns the
+// exclusive prefix and writes the block total to *total.  s_wave: >= 17 ints.
+__device__ __forceinline__ int block_scan_excl(int v, int *s_wave, int *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += x;
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int q = 0; q < nwaves; ++q) {
+            const int x = s_wave[q];
+            s_wave[q] = run;
+            run += x;
+        }
+        s_wave[16] = run;
+    }
+    __syncthreads();
+    const int excl = s_wave[wave] + incl - v;
+    *total = s_wave[16];
+    __syncthreads();
+    return excl;
+}
+
+// In-place exclusive scan of a[0..count) in LDS; a[count] receives the total.
+__device__ void lds_scan_excl(int *a, int count, int *s_wave)
+{
+    const int per = (count + blockDim.x - 1) / blockDim.x;
+    const int beg = min(count, static_cast<int>(threadIdx.x) * per);
+    const int end = min(count, beg + per);
+    int sum = 0;
+    for (int q = beg; q < end; ++q) sum += a[q];
+    int total;
+    int run = block_scan_excl(sum, s_wave, &total);
+    for (int q = beg; q < end; ++q) {
+        const int x = a[q];
+        a[q] = run;
+        run += x;
+    }
+    if (threadIdx.x == 0) a[count] = total;
+    __syncthreads();
+}
+
+// Largest q in [0, n) with a[q] <= key (a nondecreasing, a[0] <= key).
+__device__ __forceinline__ int find_segment(const int *a, int n, int key)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t load_word(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_word(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll *p until `accept(word)`; false if the wait was abandoned (time-out or
+// another workgroup gave up).
+template <class Accept>
+__device__ __forceinline__ bool wait_word(const uint64_t *p, uint32_t *abort, StepCtl *ctl, Accept accept, uint64_t &w)
+{
+    uint32_t spins = 0;
+    for (;;) {
+        w = load_word(p);
+        if (accept(w)) return true;
+        if ((++spins & 1023u) == 0) {
+            if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+            if (spins > kSpinLimit) {
+                __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicOr(&ctl->flags, kFlagTimeout);
+                return false;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <int WF>
+__global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
+{
+    extern __shared__ int lds[];
+    __shared__ uint64_t s_thr[8 * kPoisMaxDev];
+    __shared__ int s_wave[17];
+    __shared__ int s_abort;
+
+    const DevNet &B = P.base;
+    StepCtl *ctl = B.ctl;
+    const int t = blockIdx.x, T = P.n_tiles, tile = P.tile;
+    const int l = threadIdx.x, nthr = blockDim.x;
+    const int mask = B.ring_mask, R = mask + 1;
+    const int32_t t0 = t * tile;
+    const int tlen = min(tile, B.n - t0);
+
+    int *ring = lds;                           // [R][tile]
+    int *s_cnt = ring + R * tile;              // [T + 1] spike counts -> offsets
+    int *s_first = s_cnt + T + 1;              // [T] first spike id of each tile
+    int *s_ids = s_first + T;                  // [kSpkBatch] spike ids of the batch
+    int *s_beg = s_ids + kSpkBatch;            // [kSpkBatch] sub-row start
+    int *s_pre = s_beg + kSpkBatch;            // [kSpkBatch + 1] sub-row lengths -> offsets
+    int *s_own = s_pre + kSpkBatch + 1;        // [tile] this tile's spikes
+
+    for (int q = l; q < 8 * kPoisMaxDev; q += nthr) s_thr[q] = B.pois_thr[q];
+    for (int s = 0; s < R; ++s)
+        for (int q = l; q < tile; q += nthr)
+            ring[s * tile + q] = q < tlen ? B.ring[static_cast<size_t>(s) * B.n + t0 + q] : 0;
+    if (l == 0) s_abort = 0;
+
+    const bool own = l < tlen;
+    const int32_t i = t0 + l;
+    float u = 0.f, I = 0.f;
+    int r = 0, pop = 0, inst = 0;
+    int32_t local = 0;
+    uint64_t seed = 0;
+    if (own) {
+        const uint32_t meta = B.meta[i];
+        inst = static_cast<int>(meta >> 3);
+        pop = static_cast<int>(meta & 7u);
+        local = i - B.inst_off[inst];
+        seed = B.seeds[inst];
+        u = B.u[i];
+        I = B.cur[i];
+        r = B.refr[i];
+    }
+    const float cdc = own ? B.cdc[pop] : 0.f;
+    int64_t n = ctl->nbase;
+    int64_t rec_base = ctl->rec_total;
+    int32_t max_s = ctl->max_s;
+    unsigned long long ev_acc = 0, pois_sum = 0;
+    __syncthreads();
+    int kp = (own && B.poisson_on) ? poisson_draw(seed, n, local, s_thr + pop * kPoisMaxDev) : 0;
+
+    // Optional per-step phase timestamps (100 MHz constant clock), thread 0 only:
+    // 0 step start, 1 spikes published, 2 (unused), 3 next Poisson drawn,
+    // 4 every tile's word seen, 5 spike ids gathered, 6 delivery done,
+    // 7 spike count of the step.
+    uint64_t *tr = nullptr;
+    for (int64_t s = 0; s < steps; ++s, ++n) {
+        const int par = static_cast<int>(n & 1);
+        const uint64_t tag16 = (static_cast<uint64_t>((n + 1) & 0x7FFF) | 0x8000u);
+        const uint64_t tag32 = static_cast<uint64_t>(static_cast<uint32_t>(n + 1));
+        uint64_t *words = P.xchg + static_cast<size_t>(par) * T;
+        uint64_t *entries = P.xent + static_cast<size_t>(par) * T * tile;
+        tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * T + t) * kTraceSlots : nullptr;
+        if (tr) tr[0] = __builtin_amdgcn_s_memrealtime();
+        // ---- 1. neuron update ------------------------------------------------
+        bool spike = false;
+        if (own) {
+            int *cell = ring + static_cast<int>(n & mask) * tile + l;
+            int inq = *cell;
+            *cell = 0;
+            inq += kp * B.wq_ext;
+            pois_sum += static_cast<unsigned long long>(kp);
+            const float in = __fmul_rn(__int2float_rn(inq), 0.00390625f);
+            if (r > 0) {
+                r -= 1;
+            } else {
+                u = __fadd_rn(__fmul_rn(B.p22, u), __fmul_rn(B.p21, I));
+                if (cdc != 0.0f) u = __fadd_rn(u, cdc);
+            }
+            I = __fadd_rn(__fmul_rn(B.p11, I), in);
+            if (u > B.theta) {
+                spike = true;
+                u = 0.0f;
+                r = B.ref_steps;
+            }
+        }
+        // ---- 2. compaction and publication ---------------------------------------
+        int nspk;
+        const int pos = block_scan_excl(spike ? 1 : 0, s_wave, &nspk);
+        if (spike) {
+            s_own[pos] = i;
+            if (pos > 0) store_word(entries + static_cast<size_t>(t) * tile + pos, (tag32 << 32) | static_cast<uint32_t>(i));
+        }
+        __syncthreads();
+        if (l == 0) {
+            const uint64_t first = nspk ? static_cast<uint32_t>(s_own[0]) : 0u;
+            store_word(words + t, (tag16 << 48) | (static_cast<uint64_t>(nspk) << 32) | first);
+        }
+        if (tr) tr[1] = __builtin_amdgcn_s_memrealtime();
+        // ---- 3. next step's Poisson draw while the other tiles publish -----------
+        kp = (own && B.poisson_on) ? poisson_draw(seed, n + 1, local, s_thr + pop * kPoisMaxDev) : 0;
+        if (tr) tr[3] = __builtin_amdgcn_s_memrealtime();
+        // ---- 4. every tile's word of this step: counts and first ids --------------
+        for (int q = l; q < T; q += nthr) {
+            uint64_t w = 0;
+            if (!wait_word(words + q, P.abort, ctl, [tag16](uint64_t x) { return (x >> 48) == tag16; }, w)) {
+                s_abort = 1;
+                break;
+            }
+            s_cnt[q] = static_cast<int>((w >> 32) & 0xFFFFu);
+            s_first[q] = static_cast<int>(static_cast<uint32_t>(w));
+        }
+        __syncthreads();
+        if (s_abort) break;
+        lds_scan_excl(s_cnt, T, s_wave);
+        const int S = s_cnt[T];
+        if (tr) {
+            tr[4] = __builtin_amdgcn_s_memrealtime();
+            tr[7] = static_cast<uint64_t>(S);
+        }
+        // record this tile's spikes at their place in the step's list
+        for (int q = l; q < nspk; q += nthr) {
+            const int64_t at = rec_base + s_cnt[t] + q;
+            if (at < B.rec_cap) {
+                B.rec_id[at] = s_own[q];
+                B.rec_step[at] = static_cast<int32_t>(n);
+            } else {
+                atomicOr(&ctl->flags, kFlagRecordOverflow);
+            }
+        }
+        rec_base += S;
+        max_s = max(max_s, S);
+        // ---- 5. delivery into this tile's LDS ring -----------------------------
+        for (int b0 = 0; b0 < S; b0 += kSpkBatch) {
+            const int nb = min(kSpkBatch, S - b0);
+            for (int q = l; q < nb; q += nthr) {
+                const int g = b0 + q;
+                const int src = find_segment(s_cnt, T + 1, g);
+                const int k = g - s_cnt[src];
+                int pre = s_first[src];
+                if (k > 0) {
+                    uint64_t w = 0;
+                    if (!wait_word(entries + static_cast<size_t>(src) * tile + k, P.abort, ctl,
+                                   [tag32](uint64_t x) { return (x >> 32) == tag32; }, w)) {
+                        s_abort = 1;
+                        w = 0;
+                    }
+                    pre = static_cast<int>(static_cast<uint32_t>(w));
+                }
+                const size_t at = static_cast<size_t>(pre) * T + t;
+                const uint32_t beg = P.sub_ptr[at];
+                s_beg[q] = static_cast<int>(beg);
+                s_pre[q] = static_cast<int>(P.sub_ptr[at + 1] - beg);
+            }
+            __syncthreads();
+            if (s_abort) break;
+            if (tr && b0 == 0) tr[5] = __builtin_amdgcn_s_memrealtime();
+            lds_scan_excl(s_pre, nb, s_wave);
+            const int E = s_pre[nb];
+            ev_acc += static_cast<unsigned long long>(E);
+            for (int e = l; e < E; e += nthr) {
+                const int q = find_segment(s_pre, nb + 1, e);
+                const uint32_t j = static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(e - s_pre[q]);
+                const int tg = B.tgt[j] - t0;
+                const int d = B.dly[j];
+                const int wq = weight_q8<WF>(B.w, j);
+                atomicAdd(ring + static_cast<int>((n + d) & mask) * tile + tg, wq);
+            }
+            __syncthreads();
+        }
+        if (s_abort) break;
+        if (tr) tr[6] = __builtin_amdgcn_s_memrealtime();
+    }
+
+    // ---- write back state, ring and counters -------------------------------------
+    if (own) {
+        B.u[i] = u;
+        B.cur[i] = I;
+        B.refr[i] = static_cast<uint8_t>(r);
+    }
+    __syncthreads();
+    for (int s2 = 0; s2 < R; ++s2)
+        for (int q = l; q < tlen; q += nthr) B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = ring[s2 * tile + q];
+    unsigned long long ps = pois_sum;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
+    if ((l & 63) == 0 && ps) atomicAdd(&B.pois_acc[t], ps);
+    if (l == 0 && !s_abort) {
+        atomicAdd(&ctl->events, ev_acc);
+        if (t == 0) {
+            ctl->nbase = n;
+            ctl->rec_total = rec_base;
+            ctl->max_s = max_s;
+        }
+    }
+}
+
+// Sub-row pointers: for row i and tile t, the first synapse of row i whose
+// target is >= t * tile (rows are sorted by target).
+__global__ void k_subrow_ptr(const uint64_t *row_ptr, const int32_t *tgt, int32_t n, int tile, int T,
+                             uint32_t *sub_ptr, uint64_t m)
+{
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = static_cast<int64_t>(n) * T;
+    if (q > total) return;
+    if (q == total) { sub_ptr[q] = static_cast<uint32_t>(m); return; }
+    const int32_t i = static_cast<int32_t>(q / T);
+    const int t = static_cast<int>(q % T);
+    const int32_t key = t * tile;
+    uint64_t lo = row_ptr[i], hi = row_ptr[i + 1];
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (tgt[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    sub_ptr[q] = static_cast<uint32_t>(lo);
+}
+
+template <int WF>
+const void *tiled_fn()
+{
+    return reinterpret_cast<const void *>(&k_tiled<WF>);
+}
+
+const void *tiled_kernel(int wfmt)
+{
+    return wfmt == 0 ? tiled_fn<0>() : wfmt == 1 ? tiled_fn<1>() : tiled_fn<2>();
+}
+
+}  // namespace
+
+size_t tiled_lds_bytes(int tile, int ring, int n_tiles)
+{
+    return sizeof(int) * (static_cast<size_t>(ring) * tile + (2 * n_tiles + 1) + 3 * kSpkBatch + 1 + tile);
+}
+
+int tiled_threads_for(int tile) { return ((tile + 63) / 64) * 64; }
+
+hipError_t tiled_max_coresident(int wfmt, int threads, size_t lds, int *blocks_per_cu)
+{
+    const void *f = tiled_kernel(wfmt);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
+}
+
+hipError_t launch_subrow_ptr(const DevNet &d, int tile, int n_tiles, uint32_t *sub_ptr, uint64_t m, hipStream_t st)
+{
+    const int64_t total = static_cast<int64_t>(d.n) * n_tiles + 1;
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(k_subrow_ptr, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d.row_ptr, d.tgt, d.n,
+                       tile, n_tiles, sub_ptr, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled(const TiledNet &tn, int64_t steps, int threads, hipStream_t st)
+{
+    const size_t lds = tiled_lds_bytes(tn.tile, tn.base.ring_mask + 1, tn.n_tiles);
+    TiledNet arg = tn;
+    int64_t nsteps = steps;
+    void *args[] = {&arg, &nsteps};
+    return hipLaunchCooperativeKernel(tiled_kernel(tn.base.wfmt), dim3(tn.n_tiles), dim3(threads), args,
+                                      static_cast<unsigned>(lds), st);
+}
+
+}  // namespace mc

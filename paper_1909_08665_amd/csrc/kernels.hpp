@@ -61,13 +61,18 @@ struct TiledNet {
     DevNet base;
     int32_t tile;                     // neurons per tile
     int32_t n_tiles;
-    const uint32_t *sub_ptr;          // [n * n_tiles + 1] start of the sub-row of (pre, tile)
-    const uint16_t *ltgt;             // [m] target id local to its tile
-    int32_t *tile_cnt;                // [2][n_tiles] spikes published per tile (step parity)
-    int32_t *tile_spk;                // [2][n] spike ids published per tile (tile-major slots)
-    uint32_t *bar;                    // grid barrier arrival counter
-    int32_t *state_ring;              // [n_tiles][R][tile] ring saved between launches
+    const uint32_t *sub_ptr;          // [n * n_tiles + 1] first synapse of the sub-row (pre, tile)
+    uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first id)
+    uint64_t *xent;                   // [2][n_tiles][tile] further spike ids (tag32 | id)
+    uint32_t *abort;                  // set when a wait gives up
+    uint64_t *trace;                  // optional [trace_steps][n_tiles][8] phase timestamps
+    int32_t trace_steps;
+    int32_t pad1;
 };
+
+constexpr int kTraceSlots = 8;             // timestamps per (step, tile)
+
+constexpr uint32_t kFlagTimeout = 2u;      // a cross-tile wait gave up
 
 hipError_t launch_neuron(const DevNet &d, int block, int s_off, hipStream_t st);
 hipError_t launch_deliver(const DevNet &d, int grid, int s_off, hipStream_t st);
@@ -76,7 +81,9 @@ hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st);
 
 // Tiled engine: one cooperative launch advances `steps` steps.
 hipError_t launch_tiled(const TiledNet &t, int64_t steps, int threads, hipStream_t st);
+hipError_t launch_subrow_ptr(const DevNet &d, int tile, int n_tiles, uint32_t *sub_ptr, uint64_t m, hipStream_t st);
+hipError_t tiled_max_coresident(int wfmt, int threads, size_t lds, int *blocks_per_cu);
 int tiled_threads_for(int tile);
-size_t tiled_lds_bytes(int tile, int ring);
+size_t tiled_lds_bytes(int tile, int ring, int n_tiles);
 
 }  // namespace mc

@@ -10,9 +10,12 @@ per 0.1 ms step (Sec. 2c).
 Recipe (seeded by ``seed`` through numpy's Philox generator):
   * every post population b receives the same mean recurrent in-degree
     K_in = total_synapses / 77,169;
-  * a fraction rho/(1+rho) of it comes from the four inhibitory populations,
-    1/(1+rho) from the four excitatory ones (rho = 0.5: with the -4 inhibitory
-    weight factor, inhibition dominates);
+  * a fraction rho_b/(1+rho_b) of it comes from the four inhibitory
+    populations, 1/(1+rho_b) from the four excitatory ones; rho_b rises
+    linearly with the population's background in-degree K_ext from rho_lo (at
+    the smallest K_ext) to rho_hi (at the largest), so that populations with
+    stronger Poisson drive receive proportionally more inhibition (with the -4
+    inhibitory weight factor, inhibition dominates everywhere);
   * within each class the in-degree is split over source populations in
     proportion to N_a * U(0.5, 1.5);
   * p_ab = 1 - exp(-k_ab / N_a), so that the fixed-total-number rule
@@ -30,15 +33,22 @@ STANDIN_SEED = 20190918
 _EXC = np.array([1, 0, 1, 0, 1, 0, 1, 0], dtype=bool)
 
 
-def standin_conn_table(seed: int = STANDIN_SEED, rho: float = 0.5, total_synapses: float = 3.0e8):
+RHO_DEFAULT = (0.4, 0.8)
+
+
+def standin_conn_table(seed: int = STANDIN_SEED, rho=RHO_DEFAULT, total_synapses: float = 3.0e8):
     """Return a float64 array [8, 8]: entry [a, b] = pre population a -> post b."""
     rng = np.random.Generator(np.random.Philox(seed))
     n = np.asarray(FULL_SIZE, dtype=np.float64)
     k_in = total_synapses / n.sum()
     jitter = rng.uniform(0.5, 1.5, size=(8, 8))
+    lo, hi = (rho, rho) if np.isscalar(rho) else rho
+    kext = np.asarray(K_EXT, dtype=np.float64)
+    rho_b = lo + (hi - lo) * (kext - kext.min()) / (kext.max() - kext.min())
     p = np.zeros((8, 8))
     for b in range(8):
-        for cls, share in ((_EXC, 1.0 / (1.0 + rho)), (~_EXC, rho / (1.0 + rho))):
+        r = rho_b[b]
+        for cls, share in ((_EXC, 1.0 / (1.0 + r)), (~_EXC, r / (1.0 + r))):
             wgt = n[cls] * jitter[cls, b]
             k_ab = k_in * share * wgt / wgt.sum()
             p[cls, b] = 1.0 - np.exp(-k_ab / n[cls])
@@ -46,5 +56,7 @@ def standin_conn_table(seed: int = STANDIN_SEED, rho: float = 0.5, total_synapse
     return p
 
 
-def standin_description(seed: int = STANDIN_SEED):
-    return f"synthetic stand-in connection table (seed {seed}, inhibitory/excitatory in-degree ratio 0.5)"
+def standin_description(seed: int = STANDIN_SEED, rho=RHO_DEFAULT):
+    lo, hi = (rho, rho) if np.isscalar(rho) else rho
+    return (f"synthetic stand-in connection table (seed {seed}, inhibitory/excitatory "
+            f"in-degree ratio {lo}..{hi} rising with K_ext)")

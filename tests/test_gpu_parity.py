@@ -84,11 +84,13 @@ def test_poisson_and_lif_without_synapses(conn):
     assert net.counters()["poisson_events"] == orc.counters()["poisson_events"]
 
 
-@pytest.mark.parametrize("seed", [1, 2, 3])
-def test_raster_parity_2pct_one_second(conn, seed):
+@pytest.mark.parametrize("seed,engine", [(1, mc.ENGINE_TILED), (2, mc.ENGINE_TILED), (3, mc.ENGINE_TILED),
+                                         (1, mc.ENGINE_GRAPH)])
+def test_raster_parity_2pct_one_second(conn, seed, engine):
     """Microcircuit at 2 % (1544 neurons, ~1.2e5 synapses), 1 s = 10^4 steps."""
-    _say("2pct 1s seed", seed)
-    net = mc.Network.build(seed, 0.02, conn)
+    _say("2pct 1s seed", seed, "engine", engine)
+    net = mc.Network.build(seed, 0.02, conn, engine=engine)
+    assert net.info()["engine"] == engine
     orc = _oracle(seed, 0.02, conn)
     net.run(10000)
     orc.run(10000)
@@ -122,9 +124,12 @@ def test_split_runs_identical(conn):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("knobs", [dict(block=64, seg=64, deliver_grid=7, graph_chunk=1),
-                                   dict(block=512, seg=512, deliver_grid=4096, graph_chunk=200),
-                                   dict(block=128, seg=128, deliver_grid=300, graph_chunk=13)])
+@pytest.mark.parametrize("knobs", [dict(engine=mc.ENGINE_GRAPH, block=64, seg=64, deliver_grid=7, graph_chunk=1),
+                                   dict(engine=mc.ENGINE_GRAPH, block=512, seg=512, deliver_grid=4096, graph_chunk=200),
+                                   dict(engine=mc.ENGINE_GRAPH, block=128, seg=128, deliver_grid=300, graph_chunk=13),
+                                   dict(engine=mc.ENGINE_TILED, tile=64),
+                                   dict(engine=mc.ENGINE_TILED, tile=333),
+                                   dict(engine=mc.ENGINE_TILED, tile=512)])
 def test_launch_configuration_invariance(conn, knobs):
     _say("launch knobs", knobs)
     net = mc.Network.build(12, 0.05, conn)
@@ -135,17 +140,40 @@ def test_launch_configuration_invariance(conn, knobs):
     assert _same_run(net, orc) > 100
 
 
+def test_tile_too_large_for_lds_is_refused(conn):
+    _say("tile refusal")
+    net = mc.Network.build(12, 0.05, conn)
+    with pytest.raises(mc.MCError) as e:
+        net.set_launch(engine=mc.ENGINE_TILED, tile=1024)     # [64][1024] int32 ring > 160 KB
+    assert e.value.code == -9
+    net.run(10)                                             # the previous engine still runs
+
+
+def test_engine_switching_mid_run(conn):
+    """Alternate engines and tile sizes between runs of one network."""
+    _say("engine switching")
+    net = mc.Network.build(31, 0.05, conn)
+    orc = _oracle(31, 0.05, conn)
+    for k, knobs in enumerate([dict(engine=mc.ENGINE_TILED, tile=128), dict(engine=mc.ENGINE_GRAPH),
+                               dict(engine=mc.ENGINE_TILED, tile=512), dict(engine=mc.ENGINE_GRAPH, graph_chunk=7)]):
+        net.set_launch(**knobs)
+        net.run(250 + 37 * k)
+        orc.run(250 + 37 * k)
+        assert _same_run(net, orc) > 0
+
+
 def test_batch_instances_equal_single_runs(conn):
     seeds, scales = [101, 102, 103, 104], [0.02, 0.05, 0.013, 0.03]
-    _say("batch", seeds, scales)
-    net = mc.Network.build_batch(seeds, scales, conn)
-    net.run(1200)
-    for j, (s, sc) in enumerate(zip(seeds, scales)):
-        orc = _oracle(s, sc, conn)
-        orc.run(1200)
-        assert _same_run(net, orc, inst=j) > 0
-    tot = net.counters(-1)
-    assert tot["spikes"] == sum(net.counters(j)["spikes"] for j in range(4))
+    for engine in (mc.ENGINE_TILED, mc.ENGINE_GRAPH):
+        _say("batch", seeds, scales, "engine", engine)
+        net = mc.Network.build_batch(seeds, scales, conn, engine=engine)
+        net.run(1200)
+        for j, (s, sc) in enumerate(zip(seeds, scales)):
+            orc = _oracle(s, sc, conn)
+            orc.run(1200)
+            assert _same_run(net, orc, inst=j) > 0
+        tot = net.counters(-1)
+        assert tot["spikes"] == sum(net.counters(j)["spikes"] for j in range(4))
 
 
 def test_dc_input_hook_parity(conn):
@@ -178,6 +206,7 @@ def test_psp_and_state_override(conn):
 def test_edge_cases(conn):
     _say("edge cases")
     net = mc.Network.build(1, 1e-5, conn)             # every population has one neuron
+    assert net.info()["engine"] == mc.ENGINE_TILED and net.info()["n_tiles"] == 1
     n, m = net.size()
     assert n == 8
     net.run(0)
@@ -200,6 +229,7 @@ def test_full_scale_short_run_parity(conn):
     the first 120 steps (including the onset transient) bit-exact."""
     _say("full scale 120 steps")
     net = mc.Network.build(1, 1.0, conn)
+    assert net.info()["engine"] == mc.ENGINE_TILED
     orc = _oracle(1, 1.0, conn)
     n, m = net.size()
     assert (n, m) == (77169, orc.M)
