@@ -81,14 +81,35 @@ def step_latency(net):
             "frac_over_deadline": float((per > 100.0).mean()), "phases_us": phases}
 
 
+# Workloads: (seeds, scales, default weight format, description)
+CONFIGS = {
+    "full": "one full-scale instance",
+    "batch64": "64 independent instances at 10 % scale, seeds 1000..1063",
+    "uneven32": "32 independent instances at scales drawn from U(0.05, 0.5), seeds 2000..2031, FP16 weights",
+}
+
+
+def workload(args):
+    from synth_inputs import batch_scales
+
+    if args.config == "batch64":
+        return [1000 + j for j in range(64)], [0.1] * 64
+    if args.config == "uneven32":
+        return [2000 + j for j in range(32)], [float(x) for x in batch_scales(32, 0.05, 0.5, seed=777)]
+    return [args.seed], [args.scale]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--config", choices=sorted(CONFIGS), default="full",
+                    help="full: one full-scale instance; batch64: 64 instances at 10 %%; "
+                         "uneven32: 32 instances at scales U(5 %%, 50 %%), FP16 weights")
     ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--wfmt", choices=sorted(WFMT), default="fp32")
+    ap.add_argument("--wfmt", choices=sorted(WFMT), default=None)
     ap.add_argument("--engine", choices=["auto", "graph", "tiled"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
@@ -98,6 +119,8 @@ def main():
     ap.add_argument("--trace", type=int, default=0,
                     help="record per-step phase timestamps for the first K timed steps (tiled engine)")
     args = ap.parse_args()
+    if args.wfmt is None:
+        args.wfmt = "fp16" if args.config == "uneven32" else "fp32"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -114,19 +137,29 @@ def main():
     conn = standin_conn_table()
     engine = {"auto": mc.ENGINE_AUTO, "graph": mc.ENGINE_GRAPH, "tiled": mc.ENGINE_TILED}[args.engine]
 
+    seeds, scales = workload(args)
+    n_inst = len(seeds)
     t = time.time()
-    net = mc.Network.build(args.seed, args.scale, conn, wfmt=WFMT[args.wfmt], engine=engine)
+    if n_inst == 1:
+        net = mc.Network.build(seeds[0], scales[0], conn, wfmt=WFMT[args.wfmt], engine=engine)
+    else:
+        net = mc.Network.build_batch(seeds, scales, conn, wfmt=WFMT[args.wfmt], engine=engine)
     if args.tile:
         net.set_launch(engine=mc.ENGINE_TILED, tile=args.tile)
-    n_neurons, n_syn = net.size()
-    log(f"build+upload {time.time() - t:.1f}s: {n_neurons} neurons, {n_syn} synapses")
+    info = net.info()
+    n_neurons, n_syn = info["n_neurons"], info["n_synapses"]
+    log(f"build+upload {time.time() - t:.1f}s: {n_inst} instance(s), {n_neurons} neurons, {n_syn} synapses")
     if args.tune:
         net.tune(500)
     info = net.info()
     log("launch", {k: info[k] for k in ("engine", "tile_neurons", "n_tiles", "ring_depth", "graph_chunk", "seg")})
 
+    def drain_all():
+        for j in range(n_inst):
+            net.spikes(j)
+
     net.run(args.warmup)
-    net.spikes()
+    drain_all()
     if args.trace and info["engine"] == mc.ENGINE_TILED:
         net.set_trace(args.trace)
     c0 = net.counters()
@@ -138,10 +171,10 @@ def main():
     wall = time.perf_counter() - t0
     kernel_ms, launches = net.timing()
     c1 = net.counters()
-    st, _ = net.spikes()
+    drain_all()
     events = c1["events"] - c0["events"]
     spikes = c1["spikes"] - c0["spikes"]
-    rtf = args.steps * DT_S / wall
+    rtf = n_inst * args.steps * DT_S / wall        # instance-seconds simulated per wall second
     log(f"{args.steps} steps in {wall:.3f}s: RTF {rtf:.2f}, {events / wall:.3e} events/s, "
         f"{spikes / args.steps:.1f} spikes/step")
 
@@ -183,10 +216,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"microcircuit scale {args.scale} ({n_neurons} neurons, {n_syn} synapses), "
-                               f"{args.wfmt.upper()} weight store, {args.steps * DT_S:g} s biological time, "
-                               f"Poisson background, dt 0.1 ms",
-                   "seed": args.seed, "conn_table": standin_description(),
+        "config": {"workload": (f"microcircuit scale {scales[0]} " if n_inst == 1 else CONFIGS[args.config] + " ")
+                               + f"({n_neurons} neurons, {n_syn} synapses), {args.wfmt.upper()} weight store, "
+                               f"{args.steps * DT_S:g} s biological time, Poisson background, dt 0.1 ms",
+                   "instances": n_inst, "seed": seeds[0] if n_inst == 1 else [seeds[0], seeds[-1]],
+                   "conn_table": standin_description(),
                    "engine": "tiled" if tiled else "graph", "tile": info["tile_neurons"],
                    "n_tiles": info["n_tiles"], "ring_depth": info["ring_depth"]},
         "events_per_s": round(events / wall, 1),
@@ -199,7 +233,11 @@ def main():
         out["step_latency"] = latency
     net.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.seed, args.scale, conn, args.cpu_warm, args.cpu_steps)
+        # one instance of the workload (the first) on the host cores, scaled to the batch
+        cb = cpu_baseline(seeds[0], scales[0], conn, args.cpu_warm, args.cpu_steps)
+        if n_inst > 1:
+            cb["sample"] += f"; instance 0 of {n_inst} (per-instance rate)"
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

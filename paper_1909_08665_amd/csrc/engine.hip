@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -535,6 +536,213 @@ int run_graph(mc_net *nt, int64_t steps)
     return MC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Dynamic-state snapshots: device state (neuron state, rings, step control,
+// Poisson counters) plus the host-side run state.  Used by the autotuner (trials
+// run on a copy and are rolled back) and by checkpoint files.
+// ---------------------------------------------------------------------------
+struct Snapshot {
+    std::vector<float> u, cur;
+    std::vector<uint8_t> refr;
+    std::vector<int32_t> ring;
+    mc::StepCtl ctl{};
+    std::vector<unsigned long long> pois;
+    int64_t step = 0;
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;
+    std::vector<int64_t> inst_spikes, inst_events;
+};
+
+int take_snapshot(mc_net *nt, Snapshot &s)
+{
+    const int64_t N = nt->host.n;
+    s.u.resize(N);
+    s.cur.resize(N);
+    s.refr.resize(N);
+    s.ring.resize(static_cast<size_t>(nt->host.ring) * N);
+    s.pois.resize(nt->pois_slots);
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    HIP_TRY(hipMemcpy(s.u.data(), nt->u, N * sizeof(float), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(s.cur.data(), nt->cur, N * sizeof(float), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(s.refr.data(), nt->refr, N, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(s.ring.data(), nt->ring, s.ring.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&s.ctl, nt->ctl, sizeof(s.ctl), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(s.pois.data(), nt->pois_acc, s.pois.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    s.step = nt->step;
+    s.unread = nt->unread;
+    s.inst_spikes = nt->inst_spikes;
+    s.inst_events = nt->inst_events;
+    return MC_OK;
+}
+
+int restore_snapshot(mc_net *nt, const Snapshot &s)
+{
+    const int64_t N = nt->host.n;
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    HIP_TRY(hipMemcpy(nt->u, s.u.data(), N * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->cur, s.cur.data(), N * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->refr, s.refr.data(), N, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->ring, s.ring.data(), s.ring.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->ctl, &s.ctl, sizeof(s.ctl), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(nt->pois_acc, s.pois.data(), s.pois.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
+    nt->step = s.step;
+    nt->unread = s.unread;
+    nt->inst_spikes = s.inst_spikes;
+    nt->inst_events = s.inst_events;
+    return MC_OK;
+}
+
+constexpr char kCkptMagic[8] = {'M', 'C', 'C', 'K', 'P', 'T', '0', '1'};
+
+template <class T>
+bool put(std::FILE *f, const T *p, size_t n) { return std::fwrite(p, sizeof(T), n, f) == n; }
+template <class T>
+bool get(std::FILE *f, T *p, size_t n) { return std::fread(p, sizeof(T), n, f) == n; }
+
+int write_checkpoint(mc_net *nt, const char *path)
+{
+    Snapshot s;
+    int rc = take_snapshot(nt, s);
+    if (rc) return rc;
+    std::FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(MC_ERR_IO, std::string("cannot open ") + path);
+    const int64_t hdr[6] = {nt->host.n, nt->host.m, nt->host.ring, nt->host.n_inst, nt->params.wfmt,
+                            static_cast<int64_t>(s.pois.size())};
+    bool ok = put(f, kCkptMagic, 8) && put(f, hdr, 6) && put(f, nt->host.seeds.data(), nt->host.seeds.size()) &&
+              put(f, nt->host.scales.data(), nt->host.scales.size()) && put(f, &s.step, 1) &&
+              put(f, s.u.data(), s.u.size()) && put(f, s.cur.data(), s.cur.size()) &&
+              put(f, s.refr.data(), s.refr.size()) && put(f, s.ring.data(), s.ring.size()) && put(f, &s.ctl, 1) &&
+              put(f, s.pois.data(), s.pois.size()) && put(f, s.inst_spikes.data(), s.inst_spikes.size()) &&
+              put(f, s.inst_events.data(), s.inst_events.size());
+    for (const auto &v : s.unread) {
+        const int64_t k = static_cast<int64_t>(v.size());
+        ok = ok && put(f, &k, 1) && put(f, v.data(), v.size());
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? MC_OK : fail(MC_ERR_IO, std::string("write failed: ") + path);
+}
+
+int read_checkpoint(mc_net *nt, const char *path)
+{
+    std::FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(MC_ERR_IO, std::string("cannot open ") + path);
+    char magic[8];
+    int64_t hdr[6];
+    Snapshot s;
+    std::vector<uint64_t> seeds(nt->host.n_inst);
+    std::vector<double> scales(nt->host.n_inst);
+    bool ok = get(f, magic, 8) && std::memcmp(magic, kCkptMagic, 8) == 0 && get(f, hdr, 6);
+    ok = ok && hdr[0] == nt->host.n && hdr[1] == nt->host.m && hdr[2] == nt->host.ring && hdr[3] == nt->host.n_inst &&
+         hdr[4] == nt->params.wfmt && hdr[5] == nt->pois_slots;
+    ok = ok && get(f, seeds.data(), seeds.size()) && get(f, scales.data(), scales.size()) &&
+         seeds == nt->host.seeds && scales == nt->host.scales;
+    if (!ok) {
+        std::fclose(f);
+        return fail(MC_ERR_ARG, "checkpoint does not belong to a network built with the same arguments");
+    }
+    const int64_t N = nt->host.n;
+    s.u.resize(N);
+    s.cur.resize(N);
+    s.refr.resize(N);
+    s.ring.resize(static_cast<size_t>(nt->host.ring) * N);
+    s.pois.resize(nt->pois_slots);
+    s.inst_spikes.resize(nt->host.n_inst);
+    s.inst_events.resize(nt->host.n_inst);
+    s.unread.resize(nt->host.n_inst);
+    ok = get(f, &s.step, 1) && get(f, s.u.data(), N) && get(f, s.cur.data(), N) && get(f, s.refr.data(), N) &&
+         get(f, s.ring.data(), s.ring.size()) && get(f, &s.ctl, 1) && get(f, s.pois.data(), s.pois.size()) &&
+         get(f, s.inst_spikes.data(), s.inst_spikes.size()) && get(f, s.inst_events.data(), s.inst_events.size());
+    for (auto &v : s.unread) {
+        int64_t k = 0;
+        ok = ok && get(f, &k, 1) && k >= 0 && k < (int64_t{1} << 40);
+        if (!ok) break;
+        v.resize(static_cast<size_t>(k));
+        ok = get(f, v.data(), v.size());
+    }
+    std::fclose(f);
+    if (!ok) return fail(MC_ERR_IO, std::string("truncated checkpoint: ") + path);
+    return restore_snapshot(nt, s);
+}
+
+int run_engine(mc_net *nt, int64_t steps)
+{
+    return nt->engine == MC_ENGINE_TILED ? run_tiled(nt, steps) : run_graph(nt, steps);
+}
+
+// A launch configuration the tuner can select.
+struct Candidate {
+    int engine, tile, graph_chunk, seg, block, grid;
+};
+
+int apply_candidate(mc_net *nt, const Candidate &c)
+{
+    if (c.engine == MC_ENGINE_TILED) {
+        const int rc = setup_tiled(nt, c.tile);
+        if (rc) return rc;
+        nt->engine = MC_ENGINE_TILED;
+        return MC_OK;
+    }
+    if (nt->graph_chunk != c.graph_chunk || nt->seg != c.seg || nt->block != c.block || nt->deliver_grid != c.grid) {
+        nt->graph_chunk = c.graph_chunk;
+        nt->seg = c.seg;
+        nt->block = c.block;
+        nt->deliver_grid = c.grid;
+        if (nt->graph_exec) {
+            hipGraphExecDestroy(nt->graph_exec);
+            nt->graph_exec = nullptr;
+            nt->graph_k = 0;
+        }
+    }
+    nt->engine = MC_ENGINE_GRAPH;
+    return MC_OK;
+}
+
+// Time every candidate on the saved state, roll back after each trial, keep the
+// fastest.  Every candidate computes bit-identical results, so the choice only
+// changes speed.
+int autotune(mc_net *nt, int64_t trial_steps)
+{
+    Snapshot s;
+    int rc = take_snapshot(nt, s);
+    if (rc) return rc;
+    const bool timing = nt->timing;
+    nt->timing = false;
+    const int64_t seg_steps = nt->seg_steps;
+    std::vector<Candidate> cands;
+    const int64_t N = nt->host.n;
+    const int cus = nt->n_cu > 0 ? nt->n_cu : 256;
+    for (int per_cu : {1, 2, 3, 4}) {
+        const int64_t tile = std::max<int64_t>(64, (N + static_cast<int64_t>(cus) * per_cu - 1) / (static_cast<int64_t>(cus) * per_cu));
+        if (tile <= 1024) cands.push_back({MC_ENGINE_TILED, static_cast<int>(tile), 0, 0, 0, 0});
+    }
+    for (int block : {128, 256, 512})
+        for (int seg : {128, 256, 512})
+            for (int grid : {512, 2048})
+                for (int chunk : {32, 128})
+                    cands.push_back({MC_ENGINE_GRAPH, 0, chunk, seg, block, grid});
+    double best = 1e300;
+    Candidate pick{nt->engine, nt->tile, nt->graph_chunk, nt->seg, nt->block, nt->deliver_grid};
+    for (const Candidate &c : cands) {
+        if (apply_candidate(nt, c) != MC_OK) continue;       // e.g. the tile ring does not fit in LDS
+        if ((rc = restore_snapshot(nt, s))) return rc;
+        nt->seg_steps = std::max<int64_t>(trial_steps, 1);
+        if ((rc = run_engine(nt, std::max<int64_t>(8, trial_steps / 8)))) return rc;   // graph capture, warm caches
+        if ((rc = restore_snapshot(nt, s))) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        if ((rc = run_engine(nt, trial_steps))) return rc;
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (dt < best) {
+            best = dt;
+            pick = c;
+        }
+    }
+    g_err.clear();
+    if ((rc = apply_candidate(nt, pick))) return rc;
+    nt->seg_steps = seg_steps;
+    nt->timing = timing;
+    nt->overflow = false;
+    return restore_snapshot(nt, s);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -842,23 +1050,21 @@ int mc_get_timing(mc_net *net, double *kernel_ms, int64_t *launches)
 
 int mc_tune(mc_net *net, int64_t trial_steps)
 {
-    (void)trial_steps;
     if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
-    return fail(MC_ERR_UNSUPPORTED, "autotuner not available");
+    if (trial_steps < 1 || trial_steps > 100000) return fail(MC_ERR_ARG, "trial_steps must be in [1, 100000]");
+    return autotune(net, trial_steps);
 }
 
 int mc_save_state(mc_net *net, const char *path)
 {
-    (void)path;
-    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
-    return fail(MC_ERR_UNSUPPORTED, "checkpointing not available");
+    if (!net || !path) return fail(MC_ERR_ARG, "net and path must not be NULL");
+    return write_checkpoint(net, path);
 }
 
 int mc_load_state(mc_net *net, const char *path)
 {
-    (void)path;
-    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
-    return fail(MC_ERR_UNSUPPORTED, "checkpointing not available");
+    if (!net || !path) return fail(MC_ERR_ARG, "net and path must not be NULL");
+    return read_checkpoint(net, path);
 }
 
 void mc_free(mc_net *net) { release(net); }

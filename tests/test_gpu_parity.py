@@ -248,3 +248,41 @@ def test_full_scale_short_run_parity(conn):
     net.run(120)
     orc.run(120)
     assert _same_run(net, orc) > 0
+
+
+def test_checkpoint_resume_is_bit_exact(conn, tmp_path):
+    _say("checkpoint")
+    path = str(tmp_path / "net.ckpt")
+    a = mc.Network.build(41, 0.05, conn)
+    a.run(500)
+    a.spikes()
+    a.save(path)
+    a.run(700)
+    sa = a.spikes()
+    ua = a.state()
+    b = mc.Network.build(41, 0.05, conn, engine=mc.ENGINE_GRAPH)     # resume on the other engine
+    b.load(path)
+    b.run(700)
+    sb = b.spikes()
+    assert len(sa[0]) > 0
+    assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1])
+    for x, y in zip(ua, b.state()):
+        assert np.array_equal(x, y)
+    assert a.counters() == b.counters()
+    other = mc.Network.build(42, 0.05, conn)
+    with pytest.raises(mc.MCError) as e:
+        other.load(path)
+    assert e.value.code == -1
+
+
+def test_autotuner_keeps_results(conn):
+    _say("autotune")
+    net = mc.Network.build(43, 0.05, conn)
+    orc = _oracle(43, 0.05, conn)
+    net.run(300)
+    orc.run(300)
+    net.tune(200)                     # trials run on a copy of the state and are rolled back
+    assert net.counters()["steps"] == 300
+    net.run(900)
+    orc.run(900)
+    assert _same_run(net, orc) > 0
