@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-warm", type=int, default=1000)
     ap.add_argument("--cpu-steps", type=int, default=5000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device twice (reference for HBM byte counters) and exit")
     ap.add_argument("--trace", type=int, default=0,
                     help="record per-step phase timestamps for the first K timed steps (tiled engine)")
     args = ap.parse_args()
@@ -134,6 +136,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 2}), flush=True)
+        return
     conn = standin_conn_table()
     engine = {"auto": mc.ENGINE_AUTO, "graph": mc.ENGINE_GRAPH, "tiled": mc.ENGINE_TILED}[args.engine]
 

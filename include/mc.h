@@ -104,7 +104,8 @@ typedef struct mc_counters {
     int64_t spikes;              /* spikes emitted (recurrent sources) */
     int64_t events;              /* synaptic events: sum of out-degrees of spiking neurons (Sec. 3c) */
     int64_t poisson_events;      /* background spikes drawn (whole network, all instances) */
-    int64_t max_spikes_per_step; /* largest spike count in one step (whole network) */
+    int64_t max_spikes_per_step; /* largest spike count in one step (of `instance`, or of the
+                                    whole network for instance = -1) */
 } mc_counters;
 
 typedef struct mc_info {
@@ -114,18 +115,21 @@ typedef struct mc_info {
     int32_t wfmt;
     int64_t n_neurons;           /* all instances */
     int64_t n_synapses;          /* all instances */
-    int32_t tile_neurons;        /* TILED engine: neurons per workgroup tile (0 otherwise) */
-    int32_t n_tiles;
+    int32_t tile_neurons;        /* TILED engine: largest tile, neurons (0 otherwise) */
+    int32_t n_tiles;             /* TILED engine: workgroups (tiles never straddle instances) */
     int32_t graph_chunk;         /* GRAPH engine: steps per captured graph */
     int32_t seg;                 /* GRAPH engine: synapses per delivery work item */
     int32_t block;               /* GRAPH engine: threads per block of the neuron kernel */
     int32_t deliver_grid;        /* GRAPH engine: blocks of the delivery kernel */
+    int32_t lds_ring;            /* TILED engine: 1 ring in LDS, 0 ring in global memory */
 } mc_info;
 
 /* Launch knobs chosen by the autotuner or set by hand (0 = keep current). */
 typedef struct mc_launch {
     int32_t engine;
-    int32_t tile;                /* TILED engine: neurons per tile, 64..1024 */
+    int32_t tile;                /* TILED engine: at most this many neurons per tile, 16..4096 */
+    int32_t ring;                /* TILED engine: 0 auto, 1 ring in LDS, 2 ring in global memory
+                                    owned by the tile's workgroup */
     int32_t graph_chunk;         /* 1..1024 */
     int32_t seg;                 /* 64, 128, 256 or 512 */
     int32_t block;               /* 64, 128, 256 or 512 */
@@ -185,9 +189,9 @@ int mc_set_state(struct mc_net *net, int32_t instance, const float *u_mv, const 
                  const int32_t *refr, int64_t n);
 
 /*
- * Counters of `instance` (spikes, events) over the spikes recorded so far;
- * instance = -1 gives the whole network.  poisson_events and
- * max_spikes_per_step are always whole-network values.
+ * Counters of `instance` (spikes, events, largest step) over the spikes
+ * recorded so far; instance = -1 gives the whole network.  poisson_events is
+ * always the whole-network value.
  */
 int mc_get_counters(struct mc_net *net, int32_t instance, mc_counters *out);
 

@@ -141,6 +141,9 @@ typedef struct {
     double tau_m_ms, c_m_pf, tau_syn_ms, t_ref_ms, theta_mv;
     double w_mean_pa, w_sd_pa, g, l4e_l23e_factor, w_ext_pa;
     double d_mean_exc_ms, d_sd_exc_ms, d_mean_inh_ms, d_sd_inh_ms;
+    uint64_t pois_stream;    /* second key word of the Poisson draws: 0 for the model; other
+                                values give independent background realisations on the same
+                                network (noise-floor estimates only) */
 } or_params;
 
 typedef struct {
@@ -500,7 +503,7 @@ or_net *or_build_explicit(const or_params *p, uint64_t seed, const int32_t *pop_
 /* ------------------------------------------------------------------------- */
 static int poisson_count(const or_net *nt, int pop, int64_t n, int32_t i)
 {
-    uint64_t c[4] = {(uint64_t)n, (uint64_t)i, 0, TAG_POIS}, k[2] = {nt->seed, 0}, x[4];
+    uint64_t c[4] = {(uint64_t)n, (uint64_t)i, 0, TAG_POIS}, k[2] = {nt->seed, nt->p.pois_stream}, x[4];
     or_philox(c, k, x);
     uint64_t v = x[0] >> 32;
     int cnt = 0;

@@ -44,6 +44,7 @@ class OrParams(C.Structure):
         ("l4e_l23e_factor", C.c_double), ("w_ext_pa", C.c_double),
         ("d_mean_exc_ms", C.c_double), ("d_sd_exc_ms", C.c_double),
         ("d_mean_inh_ms", C.c_double), ("d_sd_inh_ms", C.c_double),
+        ("pois_stream", C.c_uint64),
     ]
 
 
@@ -60,6 +61,7 @@ def default_params(mode=MIRROR, wfmt=W_FP32, poisson_on=True, init_mode=0, i_dc=
     p.w_mean_pa, p.w_sd_pa, p.g, p.l4e_l23e_factor = 87.8, 8.78, -4.0, 2.0
     p.w_ext_pa = 87.8
     p.d_mean_exc_ms, p.d_sd_exc_ms, p.d_mean_inh_ms, p.d_sd_inh_ms = 1.5, 0.75, 0.8, 0.4
+    p.pois_stream = 0
     for k, v in over.items():
         setattr(p, k, v)
     return p

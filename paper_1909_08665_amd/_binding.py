@@ -49,11 +49,11 @@ class McInfo(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("ring_depth", C.c_int32), ("engine", C.c_int32), ("wfmt", C.c_int32),
                 ("n_neurons", C.c_int64), ("n_synapses", C.c_int64), ("tile_neurons", C.c_int32),
                 ("n_tiles", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
-                ("deliver_grid", C.c_int32)]
+                ("deliver_grid", C.c_int32), ("lds_ring", C.c_int32)]
 
 
 class McLaunch(C.Structure):
-    _fields_ = [("engine", C.c_int32), ("tile", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
+    _fields_ = [("engine", C.c_int32), ("tile", C.c_int32), ("ring", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
                 ("deliver_grid", C.c_int32)]
 
 
@@ -187,8 +187,9 @@ class Network:
     def run(self, steps):
         _check(lib().mc_run(self._h, int(steps)))
 
-    def set_launch(self, engine=0, tile=0, graph_chunk=0, seg=0, block=0, deliver_grid=0):
-        l = McLaunch(engine, tile, graph_chunk, seg, block, deliver_grid)
+    def set_launch(self, engine=0, tile=0, ring=0, graph_chunk=0, seg=0, block=0, deliver_grid=0):
+        """ring: 0 auto, 1 tile ring in LDS, 2 tile ring in global memory (tiled engine)."""
+        l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid)
         _check(lib().mc_set_launch(self._h, C.byref(l)))
 
     def tune(self, trial_steps=200):

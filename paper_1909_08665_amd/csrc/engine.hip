@@ -79,7 +79,11 @@ struct mc_net {
     mc::StepCtl *h_ctl = nullptr;
 
     // tiled engine
-    int tile = 0, n_tiles = 0, tiled_threads = 0;
+    int tile = 0, n_tiles = 0, tile_max = 0, max_intiles = 0;
+    mc::TiledShape tiled_shape{};
+    mc::TileDesc *tiles_dev = nullptr;
+    int32_t *gring = nullptr;          // private tile rings of the global-ring variant
+    int32_t gstride = 0;
     uint32_t *sub_ptr = nullptr;
     uint64_t *xchg = nullptr, *xent = nullptr;
     uint32_t *abort_flag = nullptr;
@@ -102,7 +106,9 @@ struct mc_net {
     // host-side run state
     int64_t step = 0;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;   // per instance
-    std::vector<int64_t> inst_spikes, inst_events;
+    std::vector<int64_t> inst_spikes, inst_events, inst_max_step;
+    int64_t max_step_spikes = 0;
+    int64_t steps_in_flight = 0;      // steps of the segment being drained
     bool overflow = false;
 
     // kernel timing
@@ -166,7 +172,8 @@ void release(mc_net *nt)
     if (nt->graph_exec) hipGraphExecDestroy(nt->graph_exec);
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
-                    nt->rec_id, nt->rec_step, nt->sub_ptr, nt->xchg, nt->xent, nt->abort_flag, nt->trace};
+                    nt->rec_id, nt->rec_step, nt->sub_ptr, nt->xchg, nt->xent, nt->abort_flag, nt->trace, nt->tiles_dev,
+                    nt->gring};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (nt->h_rec_id) hipHostFree(nt->h_rec_id);
@@ -291,53 +298,132 @@ int upload(mc_net *nt, const mc_config *cfg)
     return MC_OK;
 }
 
-// Neurons per tile: one workgroup per compute unit when that fits, at least 64.
-int default_tile(const mc_net *nt)
+// Cut every instance into tiles of at most `target` neurons (ceil(N_j/target)
+// equal tiles); tiles never straddle instances.
+void plan_tiles(const mc_net *nt, int target, std::vector<mc::TileDesc> &tiles, std::vector<int64_t> &sub_base,
+                int64_t &sub_total, int &tile_max, int &max_intiles)
 {
-    const int64_t N = nt->host.n;
-    const int cus = nt->n_cu > 0 ? nt->n_cu : 256;
-    int64_t tile = (N + cus - 1) / cus;
-    tile = std::max<int64_t>(64, tile);
-    return static_cast<int>(std::min<int64_t>(tile, 1024));
+    tiles.clear();
+    sub_base.assign(nt->host.n_inst, 0);
+    sub_total = 0;
+    tile_max = 0;
+    max_intiles = 0;
+    for (int j = 0; j < nt->host.n_inst; ++j) {
+        const int32_t n0 = nt->host.inst_off[j], nn = nt->host.inst_off[j + 1] - n0;
+        const int32_t T = (nn + target - 1) / target;
+        const int32_t len = (nn + T - 1) / T;
+        sub_base[j] = sub_total;
+        const int32_t first = static_cast<int32_t>(tiles.size());
+        for (int32_t k = 0; k < T; ++k) {
+            mc::TileDesc d{};
+            d.t0 = n0 + k * len;
+            d.len = std::min(len, n0 + nn - d.t0);
+            d.itile0 = first;
+            d.intiles = T;
+            d.inst_n0 = n0;
+            d.sub_base = sub_total;
+            tiles.push_back(d);
+            tile_max = std::max(tile_max, d.len);
+        }
+        max_intiles = std::max<int>(max_intiles, T);
+        sub_total += static_cast<int64_t>(nn) * T + 1;
+    }
 }
 
-// Prepare the tiled engine for `tile` neurons per workgroup: check that the LDS
-// ring fits and that every workgroup can be resident at once, then build the
-// per-(row, tile) sub-row pointers on the device.
-int setup_tiled(mc_net *nt, int tile)
+// Prepare the tiled engine for tiles of at most `target` neurons, the ring in
+// LDS (ring_mode 1), in global memory (2) or in LDS when it fits (0): check that
+// every workgroup can be resident at once, then build the per-instance sub-row
+// pointers on the device.
+int setup_tiled(mc_net *nt, int target, int ring_mode)
 {
-    const int64_t N = nt->host.n;
-    if (tile < 64 || tile > 1024) return fail(MC_ERR_ARG, "tile must be in [64, 1024]");
+    if (target < 16 || target > 4096) return fail(MC_ERR_ARG, "tile must be in [16, 4096]");
     if (nt->host.m >= (int64_t{1} << 32)) return fail(MC_ERR_UNSUPPORTED, "tiled engine needs fewer than 2^32 synapses");
-    const int T = static_cast<int>((N + tile - 1) / tile);
-    const int threads = mc::tiled_threads_for(tile);
-    const size_t lds = mc::tiled_lds_bytes(tile, nt->host.ring, T);
+    std::vector<mc::TileDesc> tiles;
+    std::vector<int64_t> sub_base;
+    int64_t sub_total = 0;
+    int tile_max = 0, max_intiles = 0;
+    plan_tiles(nt, target, tiles, sub_base, sub_total, tile_max, max_intiles);
+    const int T = static_cast<int>(tiles.size());
     const size_t lds_static = 8 * mc::kPoisMaxDev * sizeof(uint64_t) + 32 * sizeof(int);
-    if (lds + lds_static > 160 * 1024) return fail(MC_ERR_UNSUPPORTED, "tile ring does not fit in LDS");
+    mc::TiledShape sh = mc::tiled_shape(tile_max, max_intiles, nt->host.ring, ring_mode != 2);
+    if (sh.lds + lds_static > 160 * 1024) {
+        if (ring_mode == 1) return fail(MC_ERR_UNSUPPORTED, "tile ring does not fit in LDS");
+        sh = mc::tiled_shape(tile_max, max_intiles, nt->host.ring, false);
+        if (sh.lds + lds_static > 160 * 1024) return fail(MC_ERR_UNSUPPORTED, "tile scratch does not fit in LDS");
+    }
     int per_cu = 0;
-    HIP_TRY(mc::tiled_max_coresident(nt->params.wfmt, threads, lds, &per_cu));
+    HIP_TRY(mc::tiled_max_coresident(nt->params.wfmt, sh, &per_cu));
     if (static_cast<int64_t>(per_cu) * nt->n_cu < T)
         return fail(MC_ERR_UNSUPPORTED, "tiles cannot all be resident at once (" + std::to_string(T) + " tiles)");
-    if (nt->tile == tile && nt->sub_ptr) return MC_OK;
+    if (nt->tile == target && nt->tiled_shape.lds_ring == sh.lds_ring && nt->sub_ptr) return MC_OK;
     for (void *b : {static_cast<void *>(nt->sub_ptr), static_cast<void *>(nt->xchg), static_cast<void *>(nt->xent),
-                    static_cast<void *>(nt->abort_flag)})
+                    static_cast<void *>(nt->abort_flag), static_cast<void *>(nt->tiles_dev), static_cast<void *>(nt->gring)})
         if (b) hipFree(b);
+    nt->gring = nullptr;
+    nt->gstride = 0;
     nt->sub_ptr = nullptr;
     nt->xchg = nullptr;
     nt->xent = nullptr;
     nt->abort_flag = nullptr;
+    nt->tiles_dev = nullptr;
     nt->tile = 0;
     int rc;
-    if ((rc = dalloc(&nt->sub_ptr, static_cast<size_t>(N) * T + 1)) || (rc = dalloc(&nt->xchg, 2 * T)) ||
-        (rc = dalloc(&nt->xent, static_cast<size_t>(2) * T * tile)) || (rc = dalloc(&nt->abort_flag, 1)))
+    if ((rc = dalloc(&nt->sub_ptr, static_cast<size_t>(sub_total))) || (rc = dalloc(&nt->xchg, 2 * T)) ||
+        (rc = dalloc(&nt->xent, static_cast<size_t>(2) * T * tile_max)) || (rc = dalloc(&nt->abort_flag, 1)) ||
+        (rc = dalloc(&nt->tiles_dev, T)))
         return rc;
-    HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * T * tile * sizeof(uint64_t), nt->stream));
-    HIP_TRY(mc::launch_subrow_ptr(dev_view(nt), tile, T, nt->sub_ptr, static_cast<uint64_t>(nt->host.m), nt->stream));
+    if (!sh.lds_ring) {
+        nt->gstride = ((tile_max + 31) / 32) * 32;
+        if ((rc = dalloc(&nt->gring, static_cast<size_t>(T) * nt->host.ring * nt->gstride))) return rc;
+    }
+    HIP_TRY(hipMemcpy(nt->tiles_dev, tiles.data(), T * sizeof(mc::TileDesc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * T * tile_max * sizeof(uint64_t), nt->stream));
+    const mc::DevNet d = dev_view(nt);
+    for (int j = 0; j < nt->host.n_inst; ++j) {
+        const int32_t n0 = nt->host.inst_off[j], nn = nt->host.inst_off[j + 1] - n0;
+        int first = 0;
+        while (tiles[first].inst_n0 != n0) ++first;
+        HIP_TRY(mc::launch_subrow_ptr(d, nt->tiles_dev, first, tiles[first].intiles, n0, nn, nt->sub_ptr + sub_base[j],
+                                      nt->stream));
+    }
     HIP_TRY(hipStreamSynchronize(nt->stream));
-    nt->tile = tile;
+    nt->tile = target;
     nt->n_tiles = T;
-    nt->tiled_threads = threads;
+    nt->tile_max = tile_max;
+    nt->max_intiles = max_intiles;
+    nt->tiled_shape = sh;
     return MC_OK;
+}
+
+// Smallest tile size >= `start` for which the instances need at most `cap` tiles
+// (each instance rounds its tile count up).
+int64_t fitting_tile(const mc_net *nt, int64_t cap, int64_t start)
+{
+    for (int64_t target = start; target <= 4096; target += std::max<int64_t>(1, target / 64)) {
+        int64_t tiles = 0;
+        for (int j = 0; j < nt->host.n_inst; ++j) {
+            const int64_t nn = nt->host.inst_off[j + 1] - nt->host.inst_off[j];
+            tiles += (nn + target - 1) / target;
+        }
+        if (tiles <= cap) return target;
+    }
+    return 4097;
+}
+
+// Default tiling: the ring in LDS with 1..4 workgroups per compute unit when it
+// fits; otherwise a global-memory ring with 2, 1, 3 or 4 workgroups per CU.
+int setup_tiled_default(mc_net *nt)
+{
+    const int64_t N = nt->host.n;
+    const int64_t cus = nt->n_cu > 0 ? nt->n_cu : 256;
+    for (int mode : {1, 2}) {
+        for (int per_cu : mode == 1 ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{2, 1, 3, 4}) {
+            const int64_t target = fitting_tile(nt, cus * per_cu, std::max<int64_t>(64, (N + cus * per_cu - 1) / (cus * per_cu)));
+            if (target > 4096) continue;
+            if (setup_tiled(nt, static_cast<int>(target), mode) == MC_OK) return MC_OK;
+        }
+    }
+    return fail(MC_ERR_UNSUPPORTED, "no tiling of this network fits the GPU");
 }
 
 int build_common(const uint64_t *seeds, const double *scales, int32_t n, const mc_config *cfg, mc_net **out)
@@ -371,10 +457,10 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
     nt->unread.assign(n, {});
     nt->inst_spikes.assign(n, 0);
     nt->inst_events.assign(n, 0);
+    nt->inst_max_step.assign(n, 0);
     nt->engine = MC_ENGINE_GRAPH;
     if (cfg->engine != MC_ENGINE_GRAPH) {
-        const int want = default_tile(nt);
-        rc = setup_tiled(nt, want);
+        rc = setup_tiled_default(nt);
         if (rc == MC_OK) {
             nt->engine = MC_ENGINE_TILED;
         } else if (cfg->engine == MC_ENGINE_TILED) {
@@ -387,11 +473,6 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
     return MC_OK;
 }
 
-int instance_of(const mc_net *nt, int32_t gid)
-{
-    const auto &off = nt->host.inst_off;
-    return static_cast<int>(std::upper_bound(off.begin(), off.end(), gid) - off.begin()) - 1;
-}
 
 // Copy the recorder to the host, reset it, check error flags.
 int drain(mc_net *nt)
@@ -410,12 +491,31 @@ int drain(mc_net *nt)
     HIP_TRY(hipMemcpyAsync(&nt->ctl->flags, &zflags, sizeof(zflags), hipMemcpyHostToDevice, nt->stream));
     HIP_TRY(hipStreamSynchronize(nt->stream));
     const auto &rp = nt->host.row_ptr;
+    // spikes per step, whole network and per instance, for the largest-step counters
+    const int64_t s0 = nt->step;
+    const int64_t span = std::max<int64_t>(1, nt->steps_in_flight);
+    std::vector<int32_t> per_step(static_cast<size_t>(span), 0);
+    std::vector<int32_t> per_inst_step;
+    if (nt->host.n_inst > 1) per_inst_step.assign(static_cast<size_t>(span) * nt->host.n_inst, 0);
     for (int64_t q = 0; q < got; ++q) {
         const int32_t gid = nt->h_rec_id[q];
-        const int inst = nt->host.n_inst == 1 ? 0 : instance_of(nt, gid);
-        nt->unread[inst].emplace_back(static_cast<int64_t>(nt->h_rec_step[q]), gid - nt->host.inst_off[inst]);
+        const int inst = static_cast<int>(nt->host.meta[gid] >> 3);
+        const int64_t st = nt->h_rec_step[q];
+        nt->unread[inst].emplace_back(st, gid - nt->host.inst_off[inst]);
         nt->inst_spikes[inst] += 1;
         nt->inst_events[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
+        const int64_t k = st - s0;
+        if (k >= 0 && k < span) {
+            per_step[k] += 1;
+            if (!per_inst_step.empty()) per_inst_step[static_cast<size_t>(k) * nt->host.n_inst + inst] += 1;
+        }
+    }
+    for (int64_t k = 0; k < span; ++k) {
+        nt->max_step_spikes = std::max<int64_t>(nt->max_step_spikes, per_step[k]);
+        if (nt->host.n_inst == 1) nt->inst_max_step[0] = nt->max_step_spikes;
+        else
+            for (int j = 0; j < nt->host.n_inst; ++j)
+                nt->inst_max_step[j] = std::max<int64_t>(nt->inst_max_step[j], per_inst_step[static_cast<size_t>(k) * nt->host.n_inst + j]);
     }
     if (total > nt->rec_cap || (nt->h_ctl->flags & mc::kFlagRecordOverflow)) nt->overflow = true;
     if (nt->h_ctl->flags & mc::kFlagTimeout) return fail(MC_ERR_HIP, "a cross-tile wait timed out");
@@ -435,8 +535,12 @@ int run_tiled(mc_net *nt, int64_t steps)
 {
     mc::TiledNet tn{};
     tn.base = dev_view(nt);
-    tn.tile = nt->tile;
     tn.n_tiles = nt->n_tiles;
+    tn.tile_max = nt->tile_max;
+    tn.max_intiles = nt->max_intiles;
+    tn.tiles = nt->tiles_dev;
+    tn.gring = nt->gring;
+    tn.gstride = nt->gstride;
     tn.sub_ptr = nt->sub_ptr;
     tn.xchg = nt->xchg;
     tn.xent = nt->xent;
@@ -453,7 +557,7 @@ int run_tiled(mc_net *nt, int64_t steps)
         HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint64_t), nt->stream));
         HIP_TRY(hipMemsetAsync(nt->abort_flag, 0, sizeof(uint32_t), nt->stream));
         if (nt->timing) HIP_TRY(hipEventRecord(nt->ev0, nt->stream));
-        HIP_TRY(mc::launch_tiled(tn, seg, nt->tiled_threads, nt->stream));
+        HIP_TRY(mc::launch_tiled(tn, nt->tiled_shape, seg, nt->stream));
         if (nt->timing) {
             HIP_TRY(hipEventRecord(nt->ev1, nt->stream));
             HIP_TRY(hipEventSynchronize(nt->ev1));
@@ -463,6 +567,7 @@ int run_tiled(mc_net *nt, int64_t steps)
             nt->launches += 1;
         }
         const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
+        nt->steps_in_flight = seg;
         int rc = drain(nt);
         if (rc) return rc;
         const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
@@ -527,6 +632,7 @@ int run_graph(mc_net *nt, int64_t steps)
             nt->launches += seg;
         }
         const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
+        nt->steps_in_flight = seg;
         if ((rc = drain(nt))) return rc;
         const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
         adapt_segment(nt, seg, after - before);
@@ -549,7 +655,8 @@ struct Snapshot {
     std::vector<unsigned long long> pois;
     int64_t step = 0;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;
-    std::vector<int64_t> inst_spikes, inst_events;
+    std::vector<int64_t> inst_spikes, inst_events, inst_max_step;
+    int64_t max_step_spikes = 0;
 };
 
 int take_snapshot(mc_net *nt, Snapshot &s)
@@ -571,6 +678,8 @@ int take_snapshot(mc_net *nt, Snapshot &s)
     s.unread = nt->unread;
     s.inst_spikes = nt->inst_spikes;
     s.inst_events = nt->inst_events;
+    s.inst_max_step = nt->inst_max_step;
+    s.max_step_spikes = nt->max_step_spikes;
     return MC_OK;
 }
 
@@ -588,10 +697,12 @@ int restore_snapshot(mc_net *nt, const Snapshot &s)
     nt->unread = s.unread;
     nt->inst_spikes = s.inst_spikes;
     nt->inst_events = s.inst_events;
+    nt->inst_max_step = s.inst_max_step;
+    nt->max_step_spikes = s.max_step_spikes;
     return MC_OK;
 }
 
-constexpr char kCkptMagic[8] = {'M', 'C', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr char kCkptMagic[8] = {'M', 'C', 'C', 'K', 'P', 'T', '0', '2'};
 
 template <class T>
 bool put(std::FILE *f, const T *p, size_t n) { return std::fwrite(p, sizeof(T), n, f) == n; }
@@ -612,7 +723,8 @@ int write_checkpoint(mc_net *nt, const char *path)
               put(f, s.u.data(), s.u.size()) && put(f, s.cur.data(), s.cur.size()) &&
               put(f, s.refr.data(), s.refr.size()) && put(f, s.ring.data(), s.ring.size()) && put(f, &s.ctl, 1) &&
               put(f, s.pois.data(), s.pois.size()) && put(f, s.inst_spikes.data(), s.inst_spikes.size()) &&
-              put(f, s.inst_events.data(), s.inst_events.size());
+              put(f, s.inst_events.data(), s.inst_events.size()) && put(f, s.inst_max_step.data(), s.inst_max_step.size()) &&
+              put(f, &s.max_step_spikes, 1);
     for (const auto &v : s.unread) {
         const int64_t k = static_cast<int64_t>(v.size());
         ok = ok && put(f, &k, 1) && put(f, v.data(), v.size());
@@ -647,10 +759,12 @@ int read_checkpoint(mc_net *nt, const char *path)
     s.pois.resize(nt->pois_slots);
     s.inst_spikes.resize(nt->host.n_inst);
     s.inst_events.resize(nt->host.n_inst);
+    s.inst_max_step.resize(nt->host.n_inst);
     s.unread.resize(nt->host.n_inst);
     ok = get(f, &s.step, 1) && get(f, s.u.data(), N) && get(f, s.cur.data(), N) && get(f, s.refr.data(), N) &&
          get(f, s.ring.data(), s.ring.size()) && get(f, &s.ctl, 1) && get(f, s.pois.data(), s.pois.size()) &&
-         get(f, s.inst_spikes.data(), s.inst_spikes.size()) && get(f, s.inst_events.data(), s.inst_events.size());
+         get(f, s.inst_spikes.data(), s.inst_spikes.size()) && get(f, s.inst_events.data(), s.inst_events.size()) &&
+         get(f, s.inst_max_step.data(), s.inst_max_step.size()) && get(f, &s.max_step_spikes, 1);
     for (auto &v : s.unread) {
         int64_t k = 0;
         ok = ok && get(f, &k, 1) && k >= 0 && k < (int64_t{1} << 40);
@@ -670,13 +784,13 @@ int run_engine(mc_net *nt, int64_t steps)
 
 // A launch configuration the tuner can select.
 struct Candidate {
-    int engine, tile, graph_chunk, seg, block, grid;
+    int engine, tile, ring, graph_chunk, seg, block, grid;
 };
 
 int apply_candidate(mc_net *nt, const Candidate &c)
 {
     if (c.engine == MC_ENGINE_TILED) {
-        const int rc = setup_tiled(nt, c.tile);
+        const int rc = setup_tiled(nt, c.tile, c.ring);
         if (rc) return rc;
         nt->engine = MC_ENGINE_TILED;
         return MC_OK;
@@ -710,17 +824,20 @@ int autotune(mc_net *nt, int64_t trial_steps)
     std::vector<Candidate> cands;
     const int64_t N = nt->host.n;
     const int cus = nt->n_cu > 0 ? nt->n_cu : 256;
-    for (int per_cu : {1, 2, 3, 4}) {
-        const int64_t tile = std::max<int64_t>(64, (N + static_cast<int64_t>(cus) * per_cu - 1) / (static_cast<int64_t>(cus) * per_cu));
-        if (tile <= 1024) cands.push_back({MC_ENGINE_TILED, static_cast<int>(tile), 0, 0, 0, 0});
-    }
+    for (int ring : {1, 2})
+        for (int per_cu : {1, 2, 3, 4}) {
+            const int64_t cap = static_cast<int64_t>(cus) * per_cu;
+            const int64_t tile = fitting_tile(nt, cap, std::max<int64_t>(64, (N + cap - 1) / cap));
+            if (tile <= 4096) cands.push_back({MC_ENGINE_TILED, static_cast<int>(tile), ring, 0, 0, 0, 0});
+        }
     for (int block : {128, 256, 512})
         for (int seg : {128, 256, 512})
             for (int grid : {512, 2048})
                 for (int chunk : {32, 128})
-                    cands.push_back({MC_ENGINE_GRAPH, 0, chunk, seg, block, grid});
+                    cands.push_back({MC_ENGINE_GRAPH, 0, 0, chunk, seg, block, grid});
     double best = 1e300;
-    Candidate pick{nt->engine, nt->tile, nt->graph_chunk, nt->seg, nt->block, nt->deliver_grid};
+    Candidate pick{nt->engine, nt->tile, nt->tiled_shape.lds_ring ? 1 : 2, nt->graph_chunk, nt->seg, nt->block,
+                   nt->deliver_grid};
     for (const Candidate &c : cands) {
         if (apply_candidate(nt, c) != MC_OK) continue;       // e.g. the tile ring does not fit in LDS
         if ((rc = restore_snapshot(nt, s))) return rc;
@@ -896,7 +1013,7 @@ int mc_get_counters(mc_net *net, int32_t instance, mc_counters *out)
     int64_t pe = 0;
     for (auto v : acc) pe += static_cast<int64_t>(v);
     out->poisson_events = pe;
-    out->max_spikes_per_step = c.max_s;
+    out->max_spikes_per_step = instance < 0 ? net->max_step_spikes : net->inst_max_step[instance];
     return MC_OK;
 }
 
@@ -910,7 +1027,8 @@ int mc_get_info(mc_net *net, mc_info *out)
     out->wfmt = net->params.wfmt;
     out->n_neurons = net->host.n;
     out->n_synapses = net->host.m;
-    out->tile_neurons = net->engine == MC_ENGINE_TILED ? net->tile : 0;
+    out->tile_neurons = net->engine == MC_ENGINE_TILED ? net->tile_max : 0;
+    out->lds_ring = net->engine == MC_ENGINE_TILED ? (net->tiled_shape.lds_ring ? 1 : 0) : 0;
     out->n_tiles = net->engine == MC_ENGINE_TILED ? net->n_tiles : 0;
     out->graph_chunk = net->graph_chunk;
     out->seg = net->seg;
@@ -958,7 +1076,8 @@ int mc_set_launch(mc_net *net, const mc_launch *l)
 {
     if (!net || !l) return fail(MC_ERR_ARG, "net and l must not be NULL");
     if (l->engine < 0 || l->engine > MC_ENGINE_TILED) return fail(MC_ERR_ARG, "unknown engine");
-    if (l->tile && (l->tile < 64 || l->tile > 1024)) return fail(MC_ERR_ARG, "tile must be in [64, 1024]");
+    if (l->tile && (l->tile < 16 || l->tile > 4096)) return fail(MC_ERR_ARG, "tile must be in [16, 4096]");
+    if (l->ring < 0 || l->ring > 2) return fail(MC_ERR_ARG, "ring must be 0 (auto), 1 (LDS) or 2 (global)");
     if (l->graph_chunk && (l->graph_chunk < 1 || l->graph_chunk > 1024)) return fail(MC_ERR_ARG, "graph_chunk must be in [1, 1024]");
     if (l->seg && l->seg != 64 && l->seg != 128 && l->seg != 256 && l->seg != 512) return fail(MC_ERR_ARG, "seg must be 64, 128, 256 or 512");
     if (l->block && l->block != 64 && l->block != 128 && l->block != 256 && l->block != 512) return fail(MC_ERR_ARG, "block must be 64, 128, 256 or 512");
@@ -976,10 +1095,18 @@ int mc_set_launch(mc_net *net, const mc_launch *l)
     }
     if (l->engine == MC_ENGINE_GRAPH) {
         net->engine = MC_ENGINE_GRAPH;
-    } else if (l->engine == MC_ENGINE_TILED || (l->tile && net->engine == MC_ENGINE_TILED) ||
-               (l->engine == MC_ENGINE_AUTO && l->tile)) {
-        const int tile = l->tile ? l->tile : (net->tile ? net->tile : default_tile(net));
-        const int rc = setup_tiled(net, tile);
+    } else if (l->engine == MC_ENGINE_TILED || ((l->tile || l->ring) && net->engine == MC_ENGINE_TILED) ||
+               (l->engine == MC_ENGINE_AUTO && (l->tile || l->ring))) {
+        int rc;
+        if (!l->tile && !l->ring && !net->tile) {
+            rc = setup_tiled_default(net);
+        } else {
+            // a new tile size without a ring choice picks the ring automatically;
+            // a ring choice alone keeps the current tile size
+            const int tile = l->tile ? l->tile : (net->tile ? net->tile : 256);
+            const int ring = l->ring ? l->ring : (l->tile || !net->tile ? 0 : (net->tiled_shape.lds_ring ? 1 : 2));
+            rc = setup_tiled(net, tile, ring);
+        }
         if (rc) return rc;
         net->engine = MC_ENGINE_TILED;
     }

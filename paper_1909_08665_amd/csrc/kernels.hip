@@ -270,15 +270,17 @@ hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st)
 // Tiled persistent engine.
 //
 // One workgroup per tile of consecutive neurons, all workgroups co-resident
-// (cooperative launch).  A workgroup keeps its tile's neuron state in registers
-// and its delay ring [R][tile] in LDS for the whole launch; the synapse rows stay
-// in HBM and each spiking row is read once, every tile reading only the sub-row
-// that targets its own neurons.  Per step:
+// (cooperative launch); tiles never straddle two instances of a batch.  A
+// workgroup keeps its tile's neuron state in registers and owns the tile's
+// delay ring [R][len] -- in LDS when it fits, otherwise in global memory where
+// no other workgroup ever touches it, so workgroup-scope atomics suffice.  The
+// synapse rows stay in HBM; each spiking row is read once, every tile reading
+// only the sub-row that targets its own neurons.  Per step:
 //   1. update the tile (slot read/clear in LDS, Poisson, LIF), compact spikes;
 //   2. publish the tile's spikes as self-tagged 64-bit words (below);
 //   3. draw the next step's Poisson counts while the other tiles publish;
-//   4. wait until every tile's word of this step is visible -- this is the
-//      step's only grid-wide synchronisation -- and gather the spike ids;
+//   4. wait until every tile's word of this step (tiles of the same instance)
+//      is visible -- the step's only synchronisation -- and gather the ids;
 //   5. read this tile's sub-row of every spiking row and add the weights into
 //      the LDS ring with LDS integer atomics.
 //
@@ -388,110 +390,152 @@ __device__ __forceinline__ bool wait_word(const uint64_t *p, uint32_t *abort, St
     }
 }
 
-template <int WF>
+template <int WF, bool LRING, int NPT>
 __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
 {
     extern __shared__ int lds[];
     __shared__ uint64_t s_thr[8 * kPoisMaxDev];
     __shared__ int s_wave[17];
     __shared__ int s_abort;
+    __shared__ long long s_recbase;
 
     const DevNet &B = P.base;
     StepCtl *ctl = B.ctl;
-    const int t = blockIdx.x, T = P.n_tiles, tile = P.tile;
+    const int t = blockIdx.x, tmax = P.tile_max;
+    const TileDesc td = P.tiles[t];
+    const int tl = t - td.itile0, T = td.intiles;     // local tile index, tiles of the instance
     const int l = threadIdx.x, nthr = blockDim.x;
     const int mask = B.ring_mask, R = mask + 1;
-    const int32_t t0 = t * tile;
-    const int tlen = min(tile, B.n - t0);
+    const int32_t t0 = td.t0;
+    const int tlen = td.len;
 
-    int *ring = lds;                           // [R][tile]
-    int *s_cnt = ring + R * tile;              // [T + 1] spike counts -> offsets
-    int *s_first = s_cnt + T + 1;              // [T] first spike id of each tile
-    int *s_ids = s_first + T;                  // [kSpkBatch] spike ids of the batch
-    int *s_beg = s_ids + kSpkBatch;            // [kSpkBatch] sub-row start
-    int *s_pre = s_beg + kSpkBatch;            // [kSpkBatch + 1] sub-row lengths -> offsets
-    int *s_own = s_pre + kSpkBatch + 1;        // [tile] this tile's spikes
+    int *ring = lds;                                   // [R][tmax] when LRING
+    // global-ring variant: this workgroup's private, cache-line aligned slice
+    int32_t *gring = LRING ? nullptr : P.gring + static_cast<size_t>(t) * R * P.gstride;
+    int *s_cnt = lds + (LRING ? R * tmax : 0);         // [T + 1] spike counts -> offsets
+    int *s_first = s_cnt + P.max_intiles + 1;          // [T] first spike id of each tile
+    int *s_ids = s_first + P.max_intiles;              // [kSpkBatch]
+    int *s_beg = s_ids + kSpkBatch;                    // [kSpkBatch] sub-row start
+    int *s_pre = s_beg + kSpkBatch;                    // [kSpkBatch + 1] sub-row lengths -> offsets
+    int *s_own = s_pre + kSpkBatch + 1;                // [tmax] this tile's spikes
 
     for (int q = l; q < 8 * kPoisMaxDev; q += nthr) s_thr[q] = B.pois_thr[q];
-    for (int s = 0; s < R; ++s)
-        for (int q = l; q < tile; q += nthr)
-            ring[s * tile + q] = q < tlen ? B.ring[static_cast<size_t>(s) * B.n + t0 + q] : 0;
+    for (int s = 0; s < R; ++s) {
+        if (LRING) {
+            for (int q = l; q < tmax; q += nthr)
+                ring[s * tmax + q] = q < tlen ? B.ring[static_cast<size_t>(s) * B.n + t0 + q] : 0;
+        } else {
+            for (int q = l; q < tlen; q += nthr) gring[s * P.gstride + q] = B.ring[static_cast<size_t>(s) * B.n + t0 + q];
+        }
+    }
     if (l == 0) s_abort = 0;
 
-    const bool own = l < tlen;
-    const int32_t i = t0 + l;
-    float u = 0.f, I = 0.f;
-    int r = 0, pop = 0, inst = 0;
-    int32_t local = 0;
-    uint64_t seed = 0;
-    if (own) {
-        const uint32_t meta = B.meta[i];
-        inst = static_cast<int>(meta >> 3);
-        pop = static_cast<int>(meta & 7u);
-        local = i - B.inst_off[inst];
-        seed = B.seeds[inst];
-        u = B.u[i];
-        I = B.cur[i];
-        r = B.refr[i];
+    // neurons l, l + nthr, ... of the tile
+    float u[NPT], I[NPT], cdc[NPT];
+    int r[NPT], pop[NPT], kp[NPT];
+    int32_t local[NPT];
+    uint64_t seed[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = l + k * nthr;
+        u[k] = I[k] = cdc[k] = 0.f;
+        r[k] = pop[k] = kp[k] = 0;
+        local[k] = 0;
+        seed[k] = 0;
+        if (q < tlen) {
+            const int32_t i = t0 + q;
+            const uint32_t meta = B.meta[i];
+            const int inst = static_cast<int>(meta >> 3);
+            pop[k] = static_cast<int>(meta & 7u);
+            local[k] = i - B.inst_off[inst];
+            seed[k] = B.seeds[inst];
+            u[k] = B.u[i];
+            I[k] = B.cur[i];
+            r[k] = B.refr[i];
+            cdc[k] = B.cdc[pop[k]];
+        }
     }
-    const float cdc = own ? B.cdc[pop] : 0.f;
     int64_t n = ctl->nbase;
     int64_t rec_base = ctl->rec_total;
-    int32_t max_s = ctl->max_s;
     unsigned long long ev_acc = 0, pois_sum = 0;
     __syncthreads();
-    int kp = (own && B.poisson_on) ? poisson_draw(seed, n, local, s_thr + pop * kPoisMaxDev) : 0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+        kp[k] = (l + k * nthr < tlen && B.poisson_on) ? poisson_draw(seed[k], n, local[k], s_thr + pop[k] * kPoisMaxDev) : 0;
 
     // Optional per-step phase timestamps (100 MHz constant clock), thread 0 only:
     // 0 step start, 1 spikes published, 2 (unused), 3 next Poisson drawn,
     // 4 every tile's word seen, 5 spike ids gathered, 6 delivery done,
-    // 7 spike count of the step.
+    // 7 spike count of the step (this tile's instance).
     uint64_t *tr = nullptr;
     for (int64_t s = 0; s < steps; ++s, ++n) {
         const int par = static_cast<int>(n & 1);
         const uint64_t tag16 = (static_cast<uint64_t>((n + 1) & 0x7FFF) | 0x8000u);
         const uint64_t tag32 = static_cast<uint64_t>(static_cast<uint32_t>(n + 1));
-        uint64_t *words = P.xchg + static_cast<size_t>(par) * T;
-        uint64_t *entries = P.xent + static_cast<size_t>(par) * T * tile;
-        tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * T + t) * kTraceSlots : nullptr;
+        uint64_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
+        uint64_t *entries = P.xent + (static_cast<size_t>(par) * P.n_tiles + td.itile0) * tmax;
+        const int slot = static_cast<int>(n & mask);
+        tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
         if (tr) tr[0] = __builtin_amdgcn_s_memrealtime();
         // ---- 1. neuron update ------------------------------------------------
-        bool spike = false;
-        if (own) {
-            int *cell = ring + static_cast<int>(n & mask) * tile + l;
-            int inq = *cell;
-            *cell = 0;
-            inq += kp * B.wq_ext;
-            pois_sum += static_cast<unsigned long long>(kp);
-            const float in = __fmul_rn(__int2float_rn(inq), 0.00390625f);
-            if (r > 0) {
-                r -= 1;
-            } else {
-                u = __fadd_rn(__fmul_rn(B.p22, u), __fmul_rn(B.p21, I));
-                if (cdc != 0.0f) u = __fadd_rn(u, cdc);
-            }
-            I = __fadd_rn(__fmul_rn(B.p11, I), in);
-            if (u > B.theta) {
-                spike = true;
-                u = 0.0f;
-                r = B.ref_steps;
+        bool spike[NPT];
+        int nmine = 0;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int q = l + k * nthr;
+            spike[k] = false;
+            if (q < tlen) {
+                int inq;
+                if (LRING) {
+                    int *cell = ring + slot * tmax + q;
+                    inq = *cell;
+                    *cell = 0;
+                } else {
+                    int32_t *cell = gring + slot * P.gstride + q;
+                    inq = *cell;
+                    *cell = 0;
+                }
+                inq += kp[k] * B.wq_ext;
+                pois_sum += static_cast<unsigned long long>(kp[k]);
+                const float in = __fmul_rn(__int2float_rn(inq), 0.00390625f);
+                if (r[k] > 0) {
+                    r[k] -= 1;
+                } else {
+                    u[k] = __fadd_rn(__fmul_rn(B.p22, u[k]), __fmul_rn(B.p21, I[k]));
+                    if (cdc[k] != 0.0f) u[k] = __fadd_rn(u[k], cdc[k]);
+                }
+                I[k] = __fadd_rn(__fmul_rn(B.p11, I[k]), in);
+                if (u[k] > B.theta) {
+                    spike[k] = true;
+                    u[k] = 0.0f;
+                    r[k] = B.ref_steps;
+                    ++nmine;
+                }
             }
         }
         // ---- 2. compaction and publication ---------------------------------------
         int nspk;
-        const int pos = block_scan_excl(spike ? 1 : 0, s_wave, &nspk);
-        if (spike) {
-            s_own[pos] = i;
-            if (pos > 0) store_word(entries + static_cast<size_t>(t) * tile + pos, (tag32 << 32) | static_cast<uint32_t>(i));
+        int pos = block_scan_excl(nmine, s_wave, &nspk);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (spike[k]) {
+                const int32_t i = t0 + l + k * nthr;
+                s_own[pos] = i;
+                if (pos > 0) store_word(entries + static_cast<size_t>(tl) * tmax + pos, (tag32 << 32) | static_cast<uint32_t>(i));
+                ++pos;
+            }
         }
         __syncthreads();
         if (l == 0) {
             const uint64_t first = nspk ? static_cast<uint32_t>(s_own[0]) : 0u;
-            store_word(words + t, (tag16 << 48) | (static_cast<uint64_t>(nspk) << 32) | first);
+            store_word(words + tl, (tag16 << 48) | (static_cast<uint64_t>(nspk) << 32) | first);
         }
         if (tr) tr[1] = __builtin_amdgcn_s_memrealtime();
         // ---- 3. next step's Poisson draw while the other tiles publish -----------
-        kp = (own && B.poisson_on) ? poisson_draw(seed, n + 1, local, s_thr + pop * kPoisMaxDev) : 0;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+            kp[k] = (l + k * nthr < tlen && B.poisson_on)
+                        ? poisson_draw(seed[k], n + 1, local[k], s_thr + pop[k] * kPoisMaxDev) : 0;
         if (tr) tr[3] = __builtin_amdgcn_s_memrealtime();
         // ---- 4. every tile's word of this step: counts and first ids --------------
         for (int q = l; q < T; q += nthr) {
@@ -511,19 +555,35 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             tr[4] = __builtin_amdgcn_s_memrealtime();
             tr[7] = static_cast<uint64_t>(S);
         }
-        // record this tile's spikes at their place in the step's list
-        for (int q = l; q < nspk; q += nthr) {
-            const int64_t at = rec_base + s_cnt[t] + q;
-            if (at < B.rec_cap) {
-                B.rec_id[at] = s_own[q];
-                B.rec_step[at] = static_cast<int32_t>(n);
-            } else {
-                atomicOr(&ctl->flags, kFlagRecordOverflow);
+        // record this tile's spikes.  One instance: every tile knows every count,
+        // so its place in the step's list is fixed without atomics.  Batch: each
+        // spiking tile reserves its range with one atomic.
+        if (T == P.n_tiles) {
+            for (int q = l; q < nspk; q += nthr) {
+                const int64_t at = rec_base + s_cnt[tl] + q;
+                if (at < B.rec_cap) {
+                    B.rec_id[at] = s_own[q];
+                    B.rec_step[at] = static_cast<int32_t>(n);
+                } else {
+                    atomicOr(&ctl->flags, kFlagRecordOverflow);
+                }
+            }
+            rec_base += S;
+        } else if (nspk) {
+            if (l == 0) s_recbase = static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->rec_total),
+                                                                     static_cast<unsigned long long>(nspk)));
+            __syncthreads();
+            for (int q = l; q < nspk; q += nthr) {
+                const int64_t at = s_recbase + q;
+                if (at < B.rec_cap) {
+                    B.rec_id[at] = s_own[q];
+                    B.rec_step[at] = static_cast<int32_t>(n);
+                } else {
+                    atomicOr(&ctl->flags, kFlagRecordOverflow);
+                }
             }
         }
-        rec_base += S;
-        max_s = max(max_s, S);
-        // ---- 5. delivery into this tile's LDS ring -----------------------------
+        // ---- 5. delivery into this tile's ring ----------------------------------
         for (int b0 = 0; b0 < S; b0 += kSpkBatch) {
             const int nb = min(kSpkBatch, S - b0);
             for (int q = l; q < nb; q += nthr) {
@@ -533,14 +593,14 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 int pre = s_first[src];
                 if (k > 0) {
                     uint64_t w = 0;
-                    if (!wait_word(entries + static_cast<size_t>(src) * tile + k, P.abort, ctl,
+                    if (!wait_word(entries + static_cast<size_t>(src) * tmax + k, P.abort, ctl,
                                    [tag32](uint64_t x) { return (x >> 32) == tag32; }, w)) {
                         s_abort = 1;
-                        w = 0;
+                        w = static_cast<uint32_t>(td.inst_n0);
                     }
                     pre = static_cast<int>(static_cast<uint32_t>(w));
                 }
-                const size_t at = static_cast<size_t>(pre) * T + t;
+                const int64_t at = td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T + tl;
                 const uint32_t beg = P.sub_ptr[at];
                 s_beg[q] = static_cast<int>(beg);
                 s_pre[q] = static_cast<int>(P.sub_ptr[at + 1] - beg);
@@ -557,7 +617,12 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 const int tg = B.tgt[j] - t0;
                 const int d = B.dly[j];
                 const int wq = weight_q8<WF>(B.w, j);
-                atomicAdd(ring + static_cast<int>((n + d) & mask) * tile + tg, wq);
+                const int ds = static_cast<int>((n + d) & mask);
+                if (LRING)
+                    atomicAdd(ring + ds * tmax + tg, wq);
+                else
+                    __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             __syncthreads();
         }
@@ -566,14 +631,20 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     }
 
     // ---- write back state, ring and counters -------------------------------------
-    if (own) {
-        B.u[i] = u;
-        B.cur[i] = I;
-        B.refr[i] = static_cast<uint8_t>(r);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = l + k * nthr;
+        if (q < tlen) {
+            const int32_t i = t0 + q;
+            B.u[i] = u[k];
+            B.cur[i] = I[k];
+            B.refr[i] = static_cast<uint8_t>(r[k]);
+        }
     }
     __syncthreads();
     for (int s2 = 0; s2 < R; ++s2)
-        for (int q = l; q < tlen; q += nthr) B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = ring[s2 * tile + q];
+        for (int q = l; q < tlen; q += nthr)
+            B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = LRING ? ring[s2 * tmax + q] : gring[s2 * P.gstride + q];
     unsigned long long ps = pois_sum;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
@@ -582,77 +653,98 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         atomicAdd(&ctl->events, ev_acc);
         if (t == 0) {
             ctl->nbase = n;
-            ctl->rec_total = rec_base;
-            ctl->max_s = max_s;
+            if (T == P.n_tiles) ctl->rec_total = rec_base;
         }
     }
 }
 
-// Sub-row pointers: for row i and tile t, the first synapse of row i whose
-// target is >= t * tile (rows are sorted by target).
-__global__ void k_subrow_ptr(const uint64_t *row_ptr, const int32_t *tgt, int32_t n, int tile, int T,
-                             uint32_t *sub_ptr, uint64_t m)
+// Sub-row pointers of one instance: for each of its neurons i and local tile
+// tl, the first synapse of row i whose target is >= the tile's first neuron
+// (rows are sorted by target); the final entry is the end of the instance's
+// last row.
+__global__ void k_subrow_ptr(const uint64_t *row_ptr, const int32_t *tgt, const TileDesc *tiles, int itile0,
+                             int intiles, int32_t n0, int32_t nn, uint32_t *sub)
 {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t total = static_cast<int64_t>(n) * T;
+    const int64_t total = static_cast<int64_t>(nn) * intiles;
     if (q > total) return;
-    if (q == total) { sub_ptr[q] = static_cast<uint32_t>(m); return; }
-    const int32_t i = static_cast<int32_t>(q / T);
-    const int t = static_cast<int>(q % T);
-    const int32_t key = t * tile;
+    if (q == total) {
+        sub[q] = static_cast<uint32_t>(row_ptr[n0 + nn]);
+        return;
+    }
+    const int32_t i = n0 + static_cast<int32_t>(q / intiles);
+    const int tl = static_cast<int>(q % intiles);
+    const int32_t key = tiles[itile0 + tl].t0;
     uint64_t lo = row_ptr[i], hi = row_ptr[i + 1];
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
         if (tgt[mid] < key) lo = mid + 1; else hi = mid;
     }
-    sub_ptr[q] = static_cast<uint32_t>(lo);
+    sub[q] = static_cast<uint32_t>(lo);
+}
+
+template <int WF, bool LR, int NPT>
+const void *tiled_fn3()
+{
+    return reinterpret_cast<const void *>(&k_tiled<WF, LR, NPT>);
+}
+
+template <int WF, bool LR>
+const void *tiled_fn2(int npt)
+{
+    return npt == 1 ? tiled_fn3<WF, LR, 1>() : npt == 2 ? tiled_fn3<WF, LR, 2>() : tiled_fn3<WF, LR, 4>();
 }
 
 template <int WF>
-const void *tiled_fn()
+const void *tiled_fn1(bool lr, int npt)
 {
-    return reinterpret_cast<const void *>(&k_tiled<WF>);
+    return lr ? tiled_fn2<WF, true>(npt) : tiled_fn2<WF, false>(npt);
 }
 
-const void *tiled_kernel(int wfmt)
+const void *tiled_kernel(int wfmt, bool lr, int npt)
 {
-    return wfmt == 0 ? tiled_fn<0>() : wfmt == 1 ? tiled_fn<1>() : tiled_fn<2>();
+    return wfmt == 0 ? tiled_fn1<0>(lr, npt) : wfmt == 1 ? tiled_fn1<1>(lr, npt) : tiled_fn1<2>(lr, npt);
 }
 
 }  // namespace
 
-size_t tiled_lds_bytes(int tile, int ring, int n_tiles)
+TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring)
 {
-    return sizeof(int) * (static_cast<size_t>(ring) * tile + (2 * n_tiles + 1) + 3 * kSpkBatch + 1 + tile);
+    TiledShape sh{};
+    sh.lds_ring = lds_ring;
+    sh.npt = tile_max <= 1024 ? 1 : tile_max <= 2048 ? 2 : 4;
+    const int per_thread = (tile_max + sh.npt - 1) / sh.npt;
+    sh.threads = ((per_thread + 63) / 64) * 64;
+    sh.lds = sizeof(int) * ((lds_ring ? static_cast<size_t>(ring) * tile_max : 0) + (2 * static_cast<size_t>(max_intiles) + 1) +
+                            3 * kSpkBatch + 1 + tile_max);
+    return sh;
 }
 
-int tiled_threads_for(int tile) { return ((tile + 63) / 64) * 64; }
-
-hipError_t tiled_max_coresident(int wfmt, int threads, size_t lds, int *blocks_per_cu)
+hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_cu)
 {
-    const void *f = tiled_kernel(wfmt);
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    const void *f = tiled_kernel(wfmt, sh.lds_ring, sh.npt);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, sh.threads, sh.lds);
 }
 
-hipError_t launch_subrow_ptr(const DevNet &d, int tile, int n_tiles, uint32_t *sub_ptr, uint64_t m, hipStream_t st)
+hipError_t launch_subrow_ptr(const DevNet &d, const TileDesc *tiles_dev, int itile0, int intiles, int32_t n0,
+                             int32_t nn, uint32_t *sub, hipStream_t st)
 {
-    const int64_t total = static_cast<int64_t>(d.n) * n_tiles + 1;
+    const int64_t total = static_cast<int64_t>(nn) * intiles + 1;
     const int64_t blocks = (total + 255) / 256;
-    hipLaunchKernelGGL(k_subrow_ptr, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d.row_ptr, d.tgt, d.n,
-                       tile, n_tiles, sub_ptr, m);
+    hipLaunchKernelGGL(k_subrow_ptr, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d.row_ptr, d.tgt, tiles_dev,
+                       itile0, intiles, n0, nn, sub);
     return hipGetLastError();
 }
 
-hipError_t launch_tiled(const TiledNet &tn, int64_t steps, int threads, hipStream_t st)
+hipError_t launch_tiled(const TiledNet &tn, const TiledShape &sh, int64_t steps, hipStream_t st)
 {
-    const size_t lds = tiled_lds_bytes(tn.tile, tn.base.ring_mask + 1, tn.n_tiles);
     TiledNet arg = tn;
     int64_t nsteps = steps;
     void *args[] = {&arg, &nsteps};
-    return hipLaunchCooperativeKernel(tiled_kernel(tn.base.wfmt), dim3(tn.n_tiles), dim3(threads), args,
-                                      static_cast<unsigned>(lds), st);
+    return hipLaunchCooperativeKernel(tiled_kernel(tn.base.wfmt, sh.lds_ring, sh.npt), dim3(tn.n_tiles),
+                                      dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
 }
 
 }  // namespace mc

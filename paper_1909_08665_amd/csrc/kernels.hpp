@@ -55,19 +55,34 @@ struct DevNet {
     int64_t rec_cap;
 };
 
-// Tiled persistent engine: neurons cut into tiles of `tile` neurons, one
-// workgroup per tile, input ring of the tile resident in LDS.
+// Tiled persistent engine.  Tiles are ranges of consecutive neurons that never
+// straddle two instances; a tile's workgroup exchanges spikes only with the
+// tiles of its own instance.
+struct TileDesc {
+    int32_t t0;                       // first neuron (global id)
+    int32_t len;                      // neurons in the tile
+    int32_t itile0;                   // first tile of this tile's instance
+    int32_t intiles;                  // number of tiles of the instance
+    int32_t inst_n0;                  // first neuron of the instance
+    int32_t pad;
+    int64_t sub_base;                 // sub_ptr index of (first neuron of the instance, local tile 0)
+};
+
 struct TiledNet {
     DevNet base;
-    int32_t tile;                     // neurons per tile
     int32_t n_tiles;
-    const uint32_t *sub_ptr;          // [n * n_tiles + 1] first synapse of the sub-row (pre, tile)
+    int32_t tile_max;                 // largest tile (LDS / entry stride)
+    int32_t max_intiles;              // most tiles of one instance
+    int32_t pad0;
+    const TileDesc *tiles;            // [n_tiles]
+    const uint32_t *sub_ptr;          // per instance j: [N_j * T_j + 1] first synapse of (pre, local tile)
     uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first id)
-    uint64_t *xent;                   // [2][n_tiles][tile] further spike ids (tag32 | id)
+    uint64_t *xent;                   // [2][n_tiles][tile_max] further spike ids (tag32 | id)
     uint32_t *abort;                  // set when a wait gives up
     uint64_t *trace;                  // optional [trace_steps][n_tiles][8] phase timestamps
     int32_t trace_steps;
-    int32_t pad1;
+    int32_t gstride;                  // global-ring variant: ints per slot row (multiple of 32)
+    int32_t *gring;                   // global-ring variant: [n_tiles][R][gstride], one slice per workgroup
 };
 
 constexpr int kTraceSlots = 8;             // timestamps per (step, tile)
@@ -79,11 +94,19 @@ hipError_t launch_deliver(const DevNet &d, int grid, int s_off, hipStream_t st);
 hipError_t launch_advance(const DevNet &d, int steps, hipStream_t st);
 hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st);
 
-// Tiled engine: one cooperative launch advances `steps` steps.
-hipError_t launch_tiled(const TiledNet &t, int64_t steps, int threads, hipStream_t st);
-hipError_t launch_subrow_ptr(const DevNet &d, int tile, int n_tiles, uint32_t *sub_ptr, uint64_t m, hipStream_t st);
-hipError_t tiled_max_coresident(int wfmt, int threads, size_t lds, int *blocks_per_cu);
-int tiled_threads_for(int tile);
-size_t tiled_lds_bytes(int tile, int ring, int n_tiles);
+// Tiled engine: one cooperative launch advances `steps` steps.  `lds_ring`
+// selects the ring in LDS (true) or in global memory owned by the tile's
+// workgroup; `npt` neurons per thread (1, 2 or 4).
+struct TiledShape {
+    bool lds_ring;
+    int npt;
+    int threads;
+    size_t lds;                       // dynamic LDS bytes
+};
+TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring);
+hipError_t launch_tiled(const TiledNet &t, const TiledShape &sh, int64_t steps, hipStream_t st);
+hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_cu);
+hipError_t launch_subrow_ptr(const DevNet &d, const TileDesc *tiles_dev, int itile0, int intiles, int32_t n0,
+                             int32_t n_inst_neurons, uint32_t *sub_ptr_inst, hipStream_t st);
 
 }  // namespace mc

@@ -129,7 +129,10 @@ def test_split_runs_identical(conn):
                                    dict(engine=mc.ENGINE_GRAPH, block=128, seg=128, deliver_grid=300, graph_chunk=13),
                                    dict(engine=mc.ENGINE_TILED, tile=64),
                                    dict(engine=mc.ENGINE_TILED, tile=333),
-                                   dict(engine=mc.ENGINE_TILED, tile=512)])
+                                   dict(engine=mc.ENGINE_TILED, tile=512),
+                                   dict(engine=mc.ENGINE_TILED, tile=333, ring=2),
+                                   dict(engine=mc.ENGINE_TILED, tile=2000, ring=2),
+                                   dict(engine=mc.ENGINE_TILED, tile=4000, ring=2)])
 def test_launch_configuration_invariance(conn, knobs):
     _say("launch knobs", knobs)
     net = mc.Network.build(12, 0.05, conn)
@@ -144,8 +147,10 @@ def test_tile_too_large_for_lds_is_refused(conn):
     _say("tile refusal")
     net = mc.Network.build(12, 0.05, conn)
     with pytest.raises(mc.MCError) as e:
-        net.set_launch(engine=mc.ENGINE_TILED, tile=1024)     # [64][1024] int32 ring > 160 KB
+        net.set_launch(engine=mc.ENGINE_TILED, tile=1024, ring=1)     # [64][1024] int32 ring > 160 KB
     assert e.value.code == -9
+    net.set_launch(engine=mc.ENGINE_TILED, tile=1024)             # auto: ring moves to global memory
+    assert net.info()["lds_ring"] == 0
     net.run(10)                                             # the previous engine still runs
 
 
@@ -164,16 +169,23 @@ def test_engine_switching_mid_run(conn):
 
 def test_batch_instances_equal_single_runs(conn):
     seeds, scales = [101, 102, 103, 104], [0.02, 0.05, 0.013, 0.03]
-    for engine in (mc.ENGINE_TILED, mc.ENGINE_GRAPH):
-        _say("batch", seeds, scales, "engine", engine)
+    for engine, ring in ((mc.ENGINE_TILED, 0), (mc.ENGINE_TILED, 2), (mc.ENGINE_GRAPH, 0)):
+        _say("batch", seeds, scales, "engine", engine, "ring", ring)
         net = mc.Network.build_batch(seeds, scales, conn, engine=engine)
+        if ring:
+            net.set_launch(engine=mc.ENGINE_TILED, tile=700, ring=ring)
+        info = net.info()
+        if engine == mc.ENGINE_TILED:
+            assert info["n_tiles"] >= 4 and info["lds_ring"] == (0 if ring == 2 else 1)
         net.run(1200)
         for j, (s, sc) in enumerate(zip(seeds, scales)):
             orc = _oracle(s, sc, conn)
             orc.run(1200)
             assert _same_run(net, orc, inst=j) > 0
+            assert net.counters(j)["max_spikes_per_step"] == orc.counters()["max_spikes_per_step"]
         tot = net.counters(-1)
         assert tot["spikes"] == sum(net.counters(j)["spikes"] for j in range(4))
+        assert tot["max_spikes_per_step"] >= max(net.counters(j)["max_spikes_per_step"] for j in range(4))
 
 
 def test_dc_input_hook_parity(conn):
@@ -285,4 +297,16 @@ def test_autotuner_keeps_results(conn):
     assert net.counters()["steps"] == 300
     net.run(900)
     orc.run(900)
+    assert _same_run(net, orc) > 0
+
+
+def test_full_scale_global_ring_variant(conn):
+    """Full scale with the tile rings in global memory (owner-computes)."""
+    _say("full scale global ring")
+    net = mc.Network.build(2, 1.0, conn)
+    net.set_launch(engine=mc.ENGINE_TILED, ring=2)
+    assert net.info()["lds_ring"] == 0
+    orc = _oracle(2, 1.0, conn)
+    net.run(90)
+    orc.run(90)
     assert _same_run(net, orc) > 0
