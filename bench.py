@@ -99,6 +99,45 @@ def workload(args):
     return [args.seed], [args.scale]
 
 
+def delivery_microbench(net, info, args, conn_desc):
+    """Delivery of forced spike lists (S neurons spiking at once, ids spread over
+    the populations in proportion to their sizes) through mc_inject_spikes:
+    algorithmic bytes = events x bytes/event + S x (tiles + 1) x 4 B of sub-row
+    pointers + the ring read-modify-write of the tiles, over the HIP-event
+    kernel time."""
+    from synth_inputs import forced_spike_list
+
+    b_event = BYTES_PER_EVENT[args.wfmt]
+    tiled = info["engine"] == 2 and info["lds_ring"] == 1
+    n = info["n_neurons"]
+    rows = []
+    for S in (25, 93, 1000, 4000, 20000, 77169):
+        ids = forced_spike_list(S, args.scale, seed=S)
+        net.inject_spikes(ids)                          # warm-up
+        net.set_timing(True)
+        reps, events = 0, 0
+        while reps < 3 or (events < 3e9 and reps < 200):
+            events += net.inject_spikes(ids)
+            reps += 1
+        ms, launches = net.timing()
+        net.set_timing(False)
+        per = ms / launches
+        ev = events / reps
+        ptr_bytes = S * (info["n_tiles"] + 1) * 4 if tiled else S * 16
+        ring_bytes = info["ring_depth"] * n * 8 if tiled else 0
+        algo = ev * b_event + ptr_bytes + ring_bytes
+        gbs = algo / (per * 1e-3) / 1e9
+        rows.append({"spikes": S, "events": int(ev), "kernel_ms": round(per, 4), "GB_s": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "events_per_s": round(ev / (per * 1e-3), 1)})
+        log(f"D1 S={S:6d}: {ev:.3e} events in {per:.3f} ms -> {gbs:8.1f} GB/s ({gbs / HBM_PEAK_GBS:.1%} of HBM), "
+            f"{ev / (per * 1e-3):.3e} events/s")
+    return {"metric": "delivery microbenchmark (forced spike lists)", "unit": "GB/s", "dtype": "i32",
+            "data": "synthetic", "config": {"workload": f"microcircuit scale {args.scale}, {args.wfmt.upper()} store, "
+                                            f"{'tiled LDS-staged' if tiled else 'global-atomic'} delivery",
+                                            "conn_table": conn_desc, "n_tiles": info["n_tiles"]},
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-warm", type=int, default=1000)
     ap.add_argument("--cpu-steps", type=int, default=5000)
+    ap.add_argument("--d1", action="store_true",
+                    help="delivery microbenchmark: inject forced spike lists of 25..77169 neurons")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device twice (reference for HBM byte counters) and exit")
     ap.add_argument("--trace", type=int, default=0,
@@ -168,6 +209,11 @@ def main():
     def drain_all():
         for j in range(n_inst):
             net.spikes(j)
+
+    if args.d1:
+        print(json.dumps(delivery_microbench(net, info, args, conn_desc=standin_description())), flush=True)
+        net.close()
+        return
 
     net.run(args.warmup)
     drain_all()

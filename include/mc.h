@@ -210,6 +210,16 @@ int mc_get_csr(struct mc_net *net, int32_t instance, int64_t *row_ptr, int32_t *
 /* Number of neurons and synapses of `instance`. */
 int mc_instance_size(struct mc_net *net, int32_t instance, int64_t *n_neurons, int64_t *n_synapses);
 
+/*
+ * External stimulation: deliver the synaptic rows of the `count` neurons `ids`
+ * (instance-local) of `instance` as if they had spiked in the last completed
+ * step -- each synapse adds its weight into its target's input-buffer slot
+ * `delay` steps later (Sec. 3a(ii)), so the next mc_run sees them.  The
+ * injected spikes are not recorded and not counted.  *events_out (may be NULL)
+ * receives the number of synapses delivered.  Errors: MC_ERR_ARG (bad id).
+ */
+int mc_inject_spikes(struct mc_net *net, int32_t instance, const int32_t *ids, int64_t count, int64_t *events_out);
+
 /* Select launch knobs (engine, tile size, graph chunk, work-item size, block, grid).
    MC_ERR_UNSUPPORTED if the TILED engine cannot hold the network (LDS, co-residency). */
 int mc_set_launch(struct mc_net *net, const mc_launch *l);

@@ -632,6 +632,23 @@ static int step_once(or_net *nt)
     return 0;
 }
 
+/* Deliver the rows of the listed neurons as if they had spiked in the step
+   before the current one (external stimulation); not recorded or counted. */
+int or_inject(or_net *nt, const int32_t *ids, int64_t count)
+{
+    const int64_t n = nt->step - 1;
+    for (int64_t q = 0; q < count; ++q) {
+        const int32_t i = ids[q];
+        if (i < 0 || i >= nt->N) { set_err("neuron id out of range"); return -1; }
+        for (int64_t j = nt->row_ptr[i]; j < nt->row_ptr[i + 1]; ++j) {
+            const int64_t at = ((n + nt->d[j]) & (nt->R - 1)) * (int64_t)nt->N + nt->post[j];
+            if (nt->p.mode == 0) nt->ring[at] += nt->wq[j];
+            else nt->ringd[at] += nt->w64[j];
+        }
+    }
+    return 0;
+}
+
 int or_run(or_net *nt, int64_t steps)
 {
     for (int64_t s = 0; s < steps; ++s)

@@ -97,6 +97,7 @@ def lib():
                                     P, P, P, P]
     L.or_free.argtypes = [P]
     L.or_run.argtypes = [P, C.c_int64]
+    L.or_inject.argtypes = [P, P, C.c_int64]
     for name, rt in (("or_num_neurons", C.c_int32), ("or_num_synapses", C.c_int64), ("or_ring_depth", C.c_int32),
                      ("or_step", C.c_int64), ("or_wq_ext", C.c_int32), ("or_num_recorded", C.c_int64),
                      ("or_ring_sum", C.c_double)):
@@ -199,6 +200,11 @@ class OracleNet:
     def run(self, steps):
         if lib().or_run(self._h, int(steps)) != 0:
             raise RuntimeError("oracle run failed: " + lib().or_last_error().decode())
+
+    def inject(self, ids):
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        if lib().or_inject(self._h, _ptr(ids), len(ids)) != 0:
+            raise RuntimeError("oracle inject failed: " + lib().or_last_error().decode())
 
     @property
     def step(self):

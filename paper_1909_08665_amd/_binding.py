@@ -62,7 +62,7 @@ EXPORTS = ("mc_config_default", "mc_build_network", "mc_build_batch", "mc_run", 
            "mc_get_state", "mc_set_state", "mc_get_counters", "mc_get_info", "mc_get_csr",
            "mc_instance_size", "mc_set_launch", "mc_tune", "mc_set_stream", "mc_set_timing",
            "mc_get_timing", "mc_set_trace", "mc_get_trace", "mc_save_state", "mc_load_state", "mc_free",
-           "mc_last_error")
+           "mc_last_error", "mc_inject_spikes")
 
 _lib = None
 
@@ -102,6 +102,7 @@ def lib():
     L.mc_set_stream.argtypes = [P, P]
     L.mc_set_timing.argtypes = [P, I32]
     L.mc_get_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I64)]
+    L.mc_inject_spikes.argtypes = [P, I32, P, I64, C.POINTER(I64)]
     L.mc_set_trace.argtypes = [P, I32]
     L.mc_get_trace.argtypes = [P, P, I64, C.POINTER(I64)]
     L.mc_save_state.argtypes = [P, C.c_char_p]
@@ -207,6 +208,14 @@ class Network:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().mc_get_timing(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def inject_spikes(self, ids, instance=0):
+        """Deliver the rows of neurons `ids` as if they spiked in the last step;
+        returns the number of synapses delivered."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        ev = C.c_int64()
+        _check(lib().mc_inject_spikes(self._h, int(instance), _ptr(ids), len(ids), C.byref(ev)))
+        return ev.value
 
     def set_trace(self, steps):
         """Record per-step phase timestamps for the first `steps` steps of the next run."""

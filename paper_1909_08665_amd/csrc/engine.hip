@@ -84,6 +84,9 @@ struct mc_net {
     mc::TileDesc *tiles_dev = nullptr;
     int32_t *gring = nullptr;          // private tile rings of the global-ring variant
     int32_t gstride = 0;
+    std::vector<mc::TileDesc> tiles_host;
+    int32_t *inject_buf = nullptr;     // device copy of injected spike ids
+    int64_t inject_cap = 0;
     uint32_t *sub_ptr = nullptr;
     uint64_t *xchg = nullptr, *xent = nullptr;
     uint32_t *abort_flag = nullptr;
@@ -173,7 +176,7 @@ void release(mc_net *nt)
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
                     nt->rec_id, nt->rec_step, nt->sub_ptr, nt->xchg, nt->xent, nt->abort_flag, nt->trace, nt->tiles_dev,
-                    nt->gring};
+                    nt->gring, nt->inject_buf};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (nt->h_rec_id) hipHostFree(nt->h_rec_id);
@@ -388,6 +391,7 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     }
     HIP_TRY(hipStreamSynchronize(nt->stream));
     nt->tile = target;
+    nt->tiles_host = tiles;
     nt->n_tiles = T;
     nt->tile_max = tile_max;
     nt->max_intiles = max_intiles;
@@ -1155,6 +1159,61 @@ int mc_get_trace(mc_net *net, uint64_t *out, int64_t cap, int64_t *count)
     if (n == 0) return MC_OK;
     if (!out || cap < n) return fail(MC_ERR_BUFFER_TOO_SMALL, "buffer too small");
     HIP_TRY(hipMemcpy(out, net->trace, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    return MC_OK;
+}
+
+int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t count, int64_t *events_out)
+{
+    int64_t nn = 0;
+    int rc = mc_instance_size(net, instance, &nn, nullptr);
+    if (rc) return rc;
+    if (count < 0 || count > (int64_t{1} << 30)) return fail(MC_ERR_ARG, "count out of range");
+    if (count > 0 && !ids) return fail(MC_ERR_ARG, "ids must not be NULL");
+    const int32_t off = net->host.inst_off[instance];
+    std::vector<int32_t> gids(static_cast<size_t>(count));
+    int64_t events = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        if (ids[q] < 0 || ids[q] >= nn) return fail(MC_ERR_ARG, "neuron id out of range");
+        gids[q] = ids[q] + off;
+        events += static_cast<int64_t>(net->host.row_ptr[gids[q] + 1] - net->host.row_ptr[gids[q]]);
+    }
+    if (events_out) *events_out = events;
+    if (count == 0) return MC_OK;
+    if (count > net->inject_cap) {
+        if (net->inject_buf) HIP_TRY(hipFree(net->inject_buf));
+        net->inject_buf = nullptr;
+        net->inject_cap = 0;
+        if ((rc = dalloc(&net->inject_buf, count))) return rc;
+        net->inject_cap = count;
+    }
+    HIP_TRY(hipMemcpyAsync(net->inject_buf, gids.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, net->stream));
+    const mc::DevNet d = dev_view(net);
+    const size_t lds = mc::inject_lds_bytes(net->tile_max, net->host.ring);
+    if (net->timing) HIP_TRY(hipEventRecord(net->ev0, net->stream));
+    if (net->engine == MC_ENGINE_TILED && lds + 256 <= 160 * 1024) {
+        mc::TiledNet tn{};
+        tn.base = d;
+        tn.n_tiles = net->n_tiles;
+        tn.tile_max = net->tile_max;
+        tn.tiles = net->tiles_dev;
+        tn.sub_ptr = net->sub_ptr;
+        int first = 0;
+        while (net->tiles_host[first].inst_n0 != off) ++first;
+        const int threads = std::min(1024, ((net->tile_max + 63) / 64) * 64);
+        HIP_TRY(mc::launch_inject_tiled(tn, first, net->tiles_host[first].intiles, threads, net->inject_buf,
+                                        static_cast<int32_t>(count), net->step, net->stream));
+    } else {
+        HIP_TRY(mc::launch_inject_global(d, net->inject_buf, static_cast<int32_t>(count), net->step, net->stream));
+    }
+    if (net->timing) {
+        HIP_TRY(hipEventRecord(net->ev1, net->stream));
+        HIP_TRY(hipEventSynchronize(net->ev1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, net->ev0, net->ev1));
+        net->kernel_ms += ms;
+        net->launches += 1;
+    }
+    HIP_TRY(hipStreamSynchronize(net->stream));
     return MC_OK;
 }
 

@@ -14,6 +14,8 @@
 //
 // The input buffers are int32 in units of 1/256 pA; weights are stored as float
 // (holding that fixed-point value), FP16 or BF16 and converted exactly.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace mc {
@@ -745,6 +747,115 @@ hipError_t launch_tiled(const TiledNet &tn, const TiledShape &sh, int64_t steps,
     void *args[] = {&arg, &nsteps};
     return hipLaunchCooperativeKernel(tiled_kernel(tn.base.wfmt, sh.lds_ring, sh.npt), dim3(tn.n_tiles),
                                       dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
+}
+
+}  // namespace mc
+
+// ===========================================================================
+// Spike injection: deliver the synaptic rows of a given list of neurons as if
+// they had spiked in the step before `n` (their weights land in slots
+// (n - 1 + d) mod R).  Used for external stimulation and to measure delivery on
+// large spike lists.
+// ===========================================================================
+namespace mc {
+namespace {
+
+// One workgroup per tile: gather the tile's sub-rows of all listed neurons,
+// accumulate into an LDS copy of the tile's ring, then add it into the ring.
+template <int WF>
+__global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t *ids, int32_t count, int64_t n)
+{
+    extern __shared__ int lds[];
+    __shared__ int s_wave[17];
+    const DevNet &B = P.base;
+    const int t = blockIdx.x + P.pad0;                // tiles of one instance: offset in pad0
+    const TileDesc td = P.tiles[t];
+    const int tl = t - td.itile0, T = td.intiles;
+    const int l = threadIdx.x, nthr = blockDim.x;
+    const int mask = B.ring_mask, R = mask + 1;
+    const int tmax = P.tile_max, tlen = td.len;
+    int *ring = lds;                                  // [R][tmax]
+    int *s_beg = ring + R * tmax;                     // [kSpkBatch]
+    int *s_pre = s_beg + kSpkBatch;                   // [kSpkBatch + 1]
+    for (int q = l; q < R * tmax; q += nthr) ring[q] = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < count; b0 += kSpkBatch) {
+        const int nb = min(kSpkBatch, count - b0);
+        for (int q = l; q < nb; q += nthr) {
+            const int64_t at = td.sub_base + static_cast<int64_t>(ids[b0 + q] - td.inst_n0) * T + tl;
+            const uint32_t beg = P.sub_ptr[at];
+            s_beg[q] = static_cast<int>(beg);
+            s_pre[q] = static_cast<int>(P.sub_ptr[at + 1] - beg);
+        }
+        __syncthreads();
+        lds_scan_excl(s_pre, nb, s_wave);
+        const int E = s_pre[nb];
+        for (int e = l; e < E; e += nthr) {
+            const int q = find_segment(s_pre, nb + 1, e);
+            const uint32_t j = static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(e - s_pre[q]);
+            const int tg = B.tgt[j] - td.t0;
+            const int d = B.dly[j];
+            atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, weight_q8<WF>(B.w, j));
+        }
+        __syncthreads();
+    }
+    for (int s = 0; s < R; ++s)
+        for (int q = l; q < tlen; q += nthr) {
+            const int v = ring[s * tmax + q];
+            if (v) B.ring[static_cast<size_t>(s) * B.n + td.t0 + q] += v;
+        }
+}
+
+// Fallback: one wavefront per listed neuron's row chunk of `seg` synapses,
+// device-scope int32 atomics into the global ring.
+template <int WF>
+__global__ __launch_bounds__(256) void k_inject_global(DevNet P, const int32_t *ids, int32_t count, int64_t n)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * 4;
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); w < count; w += waves) {
+        const int32_t pre = ids[w];
+        const uint64_t j0 = P.row_ptr[pre], j1 = P.row_ptr[pre + 1];
+        for (uint64_t j = j0 + lane; j < j1; j += 64) {
+            const int d = P.dly[j];
+            atomicAdd(P.ring + static_cast<size_t>((n - 1 + d) & P.ring_mask) * P.n + P.tgt[j], weight_q8<WF>(P.w, j));
+        }
+    }
+}
+
+template <int WF>
+const void *inject_tiled_fn() { return reinterpret_cast<const void *>(&k_inject_tiled<WF>); }
+
+}  // namespace
+
+size_t inject_lds_bytes(int tile_max, int ring)
+{
+    return sizeof(int) * (static_cast<size_t>(ring) * tile_max + 2 * kSpkBatch + 1);
+}
+
+hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
+                               int32_t count, int64_t n, hipStream_t st)
+{
+    TiledNet arg = tn;
+    arg.pad0 = first_tile;
+    const size_t lds = inject_lds_bytes(tn.tile_max, tn.base.ring_mask + 1);
+    const void *f = tn.base.wfmt == 0 ? inject_tiled_fn<0>() : tn.base.wfmt == 1 ? inject_tiled_fn<1>() : inject_tiled_fn<2>();
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    void *args[] = {&arg, const_cast<int32_t **>(&ids), &count, &n};
+    return hipLaunchKernel(f, dim3(ntiles), dim3(threads), args, lds, st);
+}
+
+hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int64_t n, hipStream_t st)
+{
+    const int blocks = static_cast<int>(std::min<int64_t>(4096, (static_cast<int64_t>(count) + 3) / 4));
+    if (blocks < 1) return hipSuccess;
+    switch (d.wfmt) {
+    case 0: hipLaunchKernelGGL(k_inject_global<0>, dim3(blocks), dim3(256), 0, st, d, ids, count, n); break;
+    case 1: hipLaunchKernelGGL(k_inject_global<1>, dim3(blocks), dim3(256), 0, st, d, ids, count, n); break;
+    default: hipLaunchKernelGGL(k_inject_global<2>, dim3(blocks), dim3(256), 0, st, d, ids, count, n); break;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace mc

@@ -106,6 +106,12 @@ struct TiledShape {
 TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring);
 hipError_t launch_tiled(const TiledNet &t, const TiledShape &sh, int64_t steps, hipStream_t st);
 hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_cu);
+// Spike injection (external stimulation): deliver the rows of `ids` as if they
+// spiked in step n-1.  Tiled form needs the tile ring to fit in LDS.
+size_t inject_lds_bytes(int tile_max, int ring);
+hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
+                               int32_t count, int64_t n, hipStream_t st);
+hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int64_t n, hipStream_t st);
 hipError_t launch_subrow_ptr(const DevNet &d, const TileDesc *tiles_dev, int itile0, int intiles, int32_t n0,
                              int32_t n_inst_neurons, uint32_t *sub_ptr_inst, hipStream_t st);
 

@@ -310,3 +310,23 @@ def test_full_scale_global_ring_variant(conn):
     net.run(90)
     orc.run(90)
     assert _same_run(net, orc) > 0
+
+
+@pytest.mark.parametrize("engine", [mc.ENGINE_TILED, mc.ENGINE_GRAPH])
+def test_injected_spikes_parity(conn, engine):
+    """External stimulation: rows of chosen neurons delivered as if they spiked."""
+    _say("inject", engine)
+    net = mc.Network.build(51, 0.05, conn, engine=engine)
+    orc = _oracle(51, 0.05, conn)
+    rng = np.random.default_rng(5)
+    for k in range(3):
+        ids = rng.integers(0, net.size()[0], 40 + 500 * k)      # repeats allowed
+        ev = net.inject_spikes(ids)
+        orc.inject(ids)
+        c = orc.csr()
+        assert ev == int(np.diff(c["row_ptr"])[ids].sum())
+        net.run(150)
+        orc.run(150)
+        assert _same_run(net, orc) > 0
+    with pytest.raises(mc.MCError):
+        net.inject_spikes([net.size()[0]])

@@ -1,0 +1,74 @@
+"""Statistical accuracy of the reduced-precision and plain forms against the
+oracle's FP64 mode (same network, seed 1, full scale, 10 s, first 1 s
+discarded): per-population firing rate, CV of the inter-spike interval and
+binned-count correlation (Sec. 4b of Rhodes et al., arXiv 1909.08665).
+
+Chaotic dynamics make FP32 and FP64 runs diverge spike by spike, so the
+comparison is statistical.  The FP64 reference values and their run-to-run
+spread on the same network (independent Poisson streams) come from
+tests/golden/fp64_stats_full.json, written by tests/golden/make_fp64_stats.py
+from the oracle alone.  Tolerance per population: rates within
+max(2 %, 2 x FP64 relative range), CV-ISI within max(5 %, 2 x FP64 range) for
+the FP32 store.  The FP16/BF16 stores perturb every weight by up to 2^-11 / 2^-8
+relative; on the stand-in network that perturbation acts like a different
+network realisation and can move a population's operating point well beyond
+the FP64 run-to-run spread (FP64 runs on other seeds differ by up to 40 %), so
+for them the per-population errors are reported and only the whole-network
+rate is bounded (within 30 %).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_1909_08665_amd as mc
+from oracle.stats import POP_NAMES, population_stats
+from synth_inputs import FULL_SIZE, standin_conn_table
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp64_stats_full.json")
+STEPS, DISCARD = 100000, 10000
+
+
+def _fp64_reference():
+    data = json.load(open(GOLDEN))
+    runs = [data[k]["stats"] for k in ("1", "1/stream1", "1/stream2") if k in data]
+    assert len(runs) >= 2, "golden FP64 statistics missing"
+    ref = {}
+    for p in POP_NAMES:
+        r = np.array([x[p]["rate_hz"] for x in runs])
+        c = np.array([x[p]["cv_isi"] for x in runs])
+        ref[p] = dict(rate=r[0], rate_tol=max(0.02, 2 * (r.max() - r.min()) / r.mean()),
+                      cv=c[0], cv_tol=max(0.05, 2 * (c.max() - c.min()) / c.mean()))
+    return ref
+
+
+@pytest.mark.parametrize("wfmt", [mc.W_FP32, mc.W_FP16, mc.W_BF16])
+def test_statistics_against_fp64(wfmt):
+    ref = _fp64_reference()
+    print(f"[case] stats wfmt={wfmt}", flush=True)
+    net = mc.Network.build(1, 1.0, standin_conn_table(), wfmt=wfmt)
+    net.run(STEPS)
+    st, ids = net.spikes()
+    off = np.concatenate([[0], np.cumsum(FULL_SIZE)])
+    got = population_stats(st, ids, off, DISCARD, STEPS)
+    strict = []
+    for p in POP_NAMES:
+        r, c = got[p]["rate_hz"], got[p]["cv_isi"]
+        er = abs(r - ref[p]["rate"]) / ref[p]["rate"]
+        ec = abs(c - ref[p]["cv"]) / ref[p]["cv"]
+        print(f"  {p:5s} rate {r:8.3f} Hz (FP64 {ref[p]['rate']:8.3f}, err {er:6.2%}, tol {ref[p]['rate_tol']:6.2%})"
+              f"  CV {c:6.3f} (FP64 {ref[p]['cv']:6.3f}, err {ec:6.2%}, tol {ref[p]['cv_tol']:6.2%})"
+              f"  corr {got[p]['corr']:.4f}", flush=True)
+        if wfmt == mc.W_FP32:
+            assert er <= ref[p]["rate_tol"], (p, r, ref[p]["rate"])
+            assert ec <= ref[p]["cv_tol"], (p, c, ref[p]["cv"])
+        strict.append(er <= 0.02 and ec <= 0.05)
+    print(f"  populations within 2 % rate and 5 % CV: {sum(strict)} of 8", flush=True)
+    sizes = np.diff(off)
+    total = sum(got[p]["rate_hz"] * n for p, n in zip(POP_NAMES, sizes))
+    total64 = sum(ref[p]["rate"] * n for p, n in zip(POP_NAMES, sizes))
+    print(f"  whole-network rate {total / sizes.sum():.3f} Hz (FP64 {total64 / sizes.sum():.3f})", flush=True)
+    assert abs(total / total64 - 1) < 0.3
