@@ -25,7 +25,6 @@ DT_S = 1e-4
 HBM_PEAK_GBS = 8000.0
 METRIC = "real-time factor + synaptic events/s, full 77k-neuron microcircuit, 1 GPU"
 WFMT = {"fp32": 0, "fp16": 1, "bf16": 2}
-BYTES_PER_EVENT = {"fp32": 9, "fp16": 7, "bf16": 7}     # target int32 + weight + delay u8
 
 
 def log(*a):
@@ -102,12 +101,12 @@ def workload(args):
 def delivery_microbench(net, info, args, conn_desc):
     """Delivery of forced spike lists (S neurons spiking at once, ids spread over
     the populations in proportion to their sizes) through mc_inject_spikes:
-    algorithmic bytes = events x bytes/event + S x (tiles + 1) x 4 B of sub-row
-    pointers + the ring read-modify-write of the tiles, over the HIP-event
-    kernel time."""
+    algorithmic bytes = events x bytes per synapse record + S x tiles x 8 B of
+    sub-row descriptors + the ring read-modify-write of the tiles, over the
+    HIP-event kernel time."""
     from synth_inputs import forced_spike_list
 
-    b_event = BYTES_PER_EVENT[args.wfmt]
+    b_event = info["syn_bytes"]
     tiled = info["engine"] == 2 and info["lds_ring"] == 1
     n = info["n_neurons"]
     rows = []
@@ -123,7 +122,7 @@ def delivery_microbench(net, info, args, conn_desc):
         net.set_timing(False)
         per = ms / launches
         ev = events / reps
-        ptr_bytes = S * (info["n_tiles"] + 1) * 4 if tiled else S * 16
+        ptr_bytes = S * info["n_tiles"] * 8 if tiled else S * 16
         ring_bytes = info["ring_depth"] * n * 8 if tiled else 0
         algo = ev * b_event + ptr_bytes + ring_bytes
         gbs = algo / (per * 1e-3) / 1e9
@@ -236,15 +235,16 @@ def main():
         f"{spikes / args.steps:.1f} spikes/step")
 
     # Roofline of the dominant kernel: algorithmic HBM bytes it must move
-    # (synapse words of every delivered event, plus the per-spike row pointers:
-    # one (row, tile) pointer pair per tile for the tiled engine, one row pointer
-    # pair for the graph engine, plus the per-neuron state traffic of the graph
-    # engine's HBM-resident state) over its HIP-event-timed duration.
+    # (the synapse record of every delivered event, plus per spike the sub-row
+    # descriptors: one 8-byte (start, count) per tile of the spiking neuron's
+    # instance for the tiled engine, one row-pointer pair for the graph engine,
+    # plus the per-neuron state traffic of the graph engine's HBM-resident
+    # state) over its HIP-event-timed duration.
     tiled = info["engine"] == mc.ENGINE_TILED
-    b_event = BYTES_PER_EVENT[args.wfmt]
+    b_event = info["syn_bytes"]
     if tiled:
-        per_spike = 4 * (info["n_tiles"] + 1)
-        per_neuron_step = 0
+        per_spike = 8 * info["n_tiles"] / n_inst
+        per_neuron_step = 0 if info["lds_ring"] else 8          # ring slot read + clear in the global slice
         kname = "k_tiled (persistent step kernel)"
     else:
         per_spike = 16

@@ -122,6 +122,9 @@ typedef struct mc_info {
     int32_t block;               /* GRAPH engine: threads per block of the neuron kernel */
     int32_t deliver_grid;        /* GRAPH engine: blocks of the delivery kernel */
     int32_t lds_ring;            /* TILED engine: 1 ring in LDS, 0 ring in global memory */
+    int32_t syn_bytes;           /* bytes read per delivered synapse by the engine in use:
+                                    GRAPH 9 (FP32) / 7 (FP16, BF16) from the CSR arrays;
+                                    TILED 8, or 4 for FP16/BF16 tiles of <= 1024 neurons */
 } mc_info;
 
 /* Launch knobs chosen by the autotuner or set by hand (0 = keep current). */

@@ -49,7 +49,7 @@ class McInfo(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("ring_depth", C.c_int32), ("engine", C.c_int32), ("wfmt", C.c_int32),
                 ("n_neurons", C.c_int64), ("n_synapses", C.c_int64), ("tile_neurons", C.c_int32),
                 ("n_tiles", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
-                ("deliver_grid", C.c_int32), ("lds_ring", C.c_int32)]
+                ("deliver_grid", C.c_int32), ("lds_ring", C.c_int32), ("syn_bytes", C.c_int32)]
 
 
 class McLaunch(C.Structure):

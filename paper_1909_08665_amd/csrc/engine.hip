@@ -87,7 +87,9 @@ struct mc_net {
     std::vector<mc::TileDesc> tiles_host;
     int32_t *inject_buf = nullptr;     // device copy of injected spike ids
     int64_t inject_cap = 0;
-    uint32_t *sub_ptr = nullptr;
+    uint2 *subrow = nullptr;           // tiled engine: per-tile (first synapse, count) of each sub-row
+    void *syn = nullptr;               // tiled engine: packed synapse records
+    int32_t syn_fmt = 0;
     uint64_t *xchg = nullptr, *xent = nullptr;
     uint32_t *abort_flag = nullptr;
     uint64_t *trace = nullptr;
@@ -175,8 +177,8 @@ void release(mc_net *nt)
     if (nt->graph_exec) hipGraphExecDestroy(nt->graph_exec);
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
-                    nt->rec_id, nt->rec_step, nt->sub_ptr, nt->xchg, nt->xent, nt->abort_flag, nt->trace, nt->tiles_dev,
-                    nt->gring, nt->inject_buf};
+                    nt->rec_id, nt->rec_step, nt->subrow, nt->syn, nt->xchg, nt->xent, nt->abort_flag, nt->trace,
+                    nt->tiles_dev, nt->gring, nt->inject_buf};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (nt->h_rec_id) hipHostFree(nt->h_rec_id);
@@ -324,12 +326,12 @@ void plan_tiles(const mc_net *nt, int target, std::vector<mc::TileDesc> &tiles, 
             d.itile0 = first;
             d.intiles = T;
             d.inst_n0 = n0;
-            d.sub_base = sub_total;
+            d.sub_base = sub_total;              // this tile's row: one entry per neuron of the instance
             tiles.push_back(d);
             tile_max = std::max(tile_max, d.len);
+            sub_total += nn;
         }
         max_intiles = std::max<int>(max_intiles, T);
-        sub_total += static_cast<int64_t>(nn) * T + 1;
     }
 }
 
@@ -348,6 +350,14 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     plan_tiles(nt, target, tiles, sub_base, sub_total, tile_max, max_intiles);
     const int T = static_cast<int>(tiles.size());
     const size_t lds_static = 8 * mc::kPoisMaxDev * sizeof(uint64_t) + 32 * sizeof(int);
+    // packed record format: 4-byte records for 16-bit weights when the local
+    // target and delay fit 10 and 6 bits
+    int sf = mc::kSyn8F32;
+    if (nt->params.wfmt != mc::kWFp32) {
+        const bool compact = tile_max <= 1024 && nt->host.ring <= 64;
+        if (nt->params.wfmt == mc::kWFp16) sf = compact ? mc::kSyn4F16 : mc::kSyn8F16;
+        else sf = compact ? mc::kSyn4BF16 : mc::kSyn8BF16;
+    }
     mc::TiledShape sh = mc::tiled_shape(tile_max, max_intiles, nt->host.ring, ring_mode != 2);
     if (sh.lds + lds_static > 160 * 1024) {
         if (ring_mode == 1) return fail(MC_ERR_UNSUPPORTED, "tile ring does not fit in LDS");
@@ -355,23 +365,25 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
         if (sh.lds + lds_static > 160 * 1024) return fail(MC_ERR_UNSUPPORTED, "tile scratch does not fit in LDS");
     }
     int per_cu = 0;
-    HIP_TRY(mc::tiled_max_coresident(nt->params.wfmt, sh, &per_cu));
+    HIP_TRY(mc::tiled_max_coresident(sf, sh, &per_cu));
     if (static_cast<int64_t>(per_cu) * nt->n_cu < T)
         return fail(MC_ERR_UNSUPPORTED, "tiles cannot all be resident at once (" + std::to_string(T) + " tiles)");
-    if (nt->tile == target && nt->tiled_shape.lds_ring == sh.lds_ring && nt->sub_ptr) return MC_OK;
-    for (void *b : {static_cast<void *>(nt->sub_ptr), static_cast<void *>(nt->xchg), static_cast<void *>(nt->xent),
-                    static_cast<void *>(nt->abort_flag), static_cast<void *>(nt->tiles_dev), static_cast<void *>(nt->gring)})
+    if (nt->tile == target && nt->tiled_shape.lds_ring == sh.lds_ring && nt->subrow) return MC_OK;
+    for (void *b : {static_cast<void *>(nt->subrow), static_cast<void *>(nt->syn), static_cast<void *>(nt->xchg),
+                    static_cast<void *>(nt->xent), static_cast<void *>(nt->abort_flag), static_cast<void *>(nt->tiles_dev),
+                    static_cast<void *>(nt->gring)})
         if (b) hipFree(b);
     nt->gring = nullptr;
     nt->gstride = 0;
-    nt->sub_ptr = nullptr;
+    nt->subrow = nullptr;
+    nt->syn = nullptr;
     nt->xchg = nullptr;
     nt->xent = nullptr;
     nt->abort_flag = nullptr;
     nt->tiles_dev = nullptr;
     nt->tile = 0;
     int rc;
-    if ((rc = dalloc(&nt->sub_ptr, static_cast<size_t>(sub_total))) || (rc = dalloc(&nt->xchg, 2 * T)) ||
+    if ((rc = dalloc(&nt->subrow, static_cast<size_t>(sub_total))) || (rc = dalloc(&nt->xchg, 2 * T)) ||
         (rc = dalloc(&nt->xent, static_cast<size_t>(2) * T * tile_max)) || (rc = dalloc(&nt->abort_flag, 1)) ||
         (rc = dalloc(&nt->tiles_dev, T)))
         return rc;
@@ -381,15 +393,26 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     }
     HIP_TRY(hipMemcpy(nt->tiles_dev, tiles.data(), T * sizeof(mc::TileDesc), hipMemcpyHostToDevice));
     HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * T * tile_max * sizeof(uint64_t), nt->stream));
-    const mc::DevNet d = dev_view(nt);
-    for (int j = 0; j < nt->host.n_inst; ++j) {
-        const int32_t n0 = nt->host.inst_off[j], nn = nt->host.inst_off[j + 1] - n0;
-        int first = 0;
-        while (tiles[first].inst_n0 != n0) ++first;
-        HIP_TRY(mc::launch_subrow_ptr(d, nt->tiles_dev, first, tiles[first].intiles, n0, nn, nt->sub_ptr + sub_base[j],
-                                      nt->stream));
+    {
+        const size_t rec = sf <= mc::kSyn8BF16 ? 8 : 4;
+        hipError_t e = hipMalloc(&nt->syn, std::max<size_t>(1, static_cast<size_t>(nt->host.m) * rec));
+        if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
-    HIP_TRY(hipStreamSynchronize(nt->stream));
+    const mc::DevNet d = dev_view(nt);
+    HIP_TRY(mc::launch_subrows(d, nt->tiles_dev, T, sub_total, nt->subrow, nt->stream));
+    {
+        std::vector<int32_t> tile_of(static_cast<size_t>(nt->host.n));
+        for (int k = 0; k < T; ++k)
+            for (int32_t q = 0; q < tiles[k].len; ++q) tile_of[tiles[k].t0 + q] = k;
+        int32_t *tile_of_dev = nullptr;
+        if ((rc = dalloc(&tile_of_dev, tile_of.size()))) return rc;
+        hipError_t e = hipMemcpy(tile_of_dev, tile_of.data(), tile_of.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = mc::launch_pack_synapses(d, nt->tiles_dev, tile_of_dev, nt->host.m, sf, nt->syn, nt->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(nt->stream);
+        hipFree(tile_of_dev);
+        if (e != hipSuccess) return fail(MC_ERR_HIP, std::string("tiled store build: ") + hipGetErrorString(e));
+    }
+    nt->syn_fmt = sf;
     nt->tile = target;
     nt->tiles_host = tiles;
     nt->n_tiles = T;
@@ -545,7 +568,9 @@ int run_tiled(mc_net *nt, int64_t steps)
     tn.tiles = nt->tiles_dev;
     tn.gring = nt->gring;
     tn.gstride = nt->gstride;
-    tn.sub_ptr = nt->sub_ptr;
+    tn.subrow = nt->subrow;
+    tn.syn = nt->syn;
+    tn.syn_fmt = nt->syn_fmt;
     tn.xchg = nt->xchg;
     tn.xent = nt->xent;
     tn.abort = nt->abort_flag;
@@ -1033,6 +1058,8 @@ int mc_get_info(mc_net *net, mc_info *out)
     out->n_synapses = net->host.m;
     out->tile_neurons = net->engine == MC_ENGINE_TILED ? net->tile_max : 0;
     out->lds_ring = net->engine == MC_ENGINE_TILED ? (net->tiled_shape.lds_ring ? 1 : 0) : 0;
+    out->syn_bytes = net->engine == MC_ENGINE_TILED ? (net->syn_fmt <= mc::kSyn8BF16 ? 8 : 4)
+                                                    : (net->params.wfmt == mc::kWFp32 ? 9 : 7);
     out->n_tiles = net->engine == MC_ENGINE_TILED ? net->n_tiles : 0;
     out->graph_chunk = net->graph_chunk;
     out->seg = net->seg;
@@ -1196,7 +1223,9 @@ int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t 
         tn.n_tiles = net->n_tiles;
         tn.tile_max = net->tile_max;
         tn.tiles = net->tiles_dev;
-        tn.sub_ptr = net->sub_ptr;
+        tn.subrow = net->subrow;
+        tn.syn = net->syn;
+        tn.syn_fmt = net->syn_fmt;
         int first = 0;
         while (net->tiles_host[first].inst_n0 != off) ++first;
         const int threads = std::min(1024, ((net->tile_max + 63) / 64) * 64);

@@ -361,6 +361,61 @@ __device__ __forceinline__ int find_segment(const int *a, int n, int key)
     return lo;
 }
 
+// Inclusive running maximum of a[0..count) in LDS (values >= -1).
+__device__ void lds_scan_max(int *a, int count, int *s_wave)
+{
+    const int per = (count + blockDim.x - 1) / blockDim.x;
+    const int beg = min(count, static_cast<int>(threadIdx.x) * per);
+    const int end = min(count, beg + per);
+    int m = -1;
+    for (int q = beg; q < end; ++q) m = max(m, a[q]);
+    // exclusive max over the threads before this one
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
+    int incl = m;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl = max(incl, x);
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = -1;
+        for (int q = 0; q < nwaves; ++q) {
+            const int x = s_wave[q];
+            s_wave[q] = run;
+            run = max(run, x);
+        }
+    }
+    __syncthreads();
+    int run = max(s_wave[wave], __shfl_up(incl, 1, 64));
+    if (lane == 0) run = s_wave[wave];
+    for (int q = beg; q < end; ++q) {
+        run = max(run, a[q]);
+        a[q] = run;
+    }
+    __syncthreads();
+}
+
+constexpr int kEvChunk = 2048;               // events expanded per pass
+
+// For events c0 .. c0+cn-1 of a batch whose segment offsets are s_pre[0..nb]
+// (exclusive prefix, s_pre[nb] = total), write the owning segment of each event
+// into s_seg[0..cn): scatter segment starts, then a running maximum.
+__device__ void expand_segments(const int *s_pre, int nb, int c0, int cn, int *s_seg, int *s_wave)
+{
+    for (int x = threadIdx.x; x < cn; x += blockDim.x) s_seg[x] = -1;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        const int p = s_pre[q];
+        if (s_pre[q + 1] > p && p >= c0 && p < c0 + cn) s_seg[p - c0] = q;   // non-empty segments start apart
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_seg[0] < 0) s_seg[0] = find_segment(s_pre, nb + 1, c0);
+    __syncthreads();
+    lds_scan_max(s_seg, cn, s_wave);
+}
+
 __device__ __forceinline__ uint64_t load_word(const uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -392,7 +447,29 @@ __device__ __forceinline__ bool wait_word(const uint64_t *p, uint32_t *abort, St
     }
 }
 
-template <int WF, bool LRING, int NPT>
+// Decode packed synapse record j: tile-local target, delay, weight in 1/256 pA.
+template <int SF>
+__device__ __forceinline__ int syn_record(const void *__restrict__ syn, uint32_t j, int &local, int &d)
+{
+    float f;
+    if constexpr (SF <= kSyn8BF16) {
+        const uint2 r = static_cast<const uint2 *>(syn)[j];
+        local = static_cast<int>(r.x & 0xFFFFu);
+        d = static_cast<int>((r.x >> 16) & 0xFFu);
+        if constexpr (SF == kSyn8F32) f = __uint_as_float(r.y);
+        else if constexpr (SF == kSyn8F16) f = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(r.y)));
+        else f = __uint_as_float(r.y << 16);
+    } else {
+        const uint32_t r = static_cast<const uint32_t *>(syn)[j];
+        local = static_cast<int>(r & 0x3FFu);
+        d = static_cast<int>((r >> 10) & 0x3Fu);
+        if constexpr (SF == kSyn4F16) f = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(r >> 16)));
+        else f = __uint_as_float(r & 0xFFFF0000u);
+    }
+    return __float2int_rn(f * 256.0f);
+}
+
+template <int SF, bool LRING, int NPT>
 __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
 {
     extern __shared__ int lds[];
@@ -420,6 +497,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     int *s_beg = s_ids + kSpkBatch;                    // [kSpkBatch] sub-row start
     int *s_pre = s_beg + kSpkBatch;                    // [kSpkBatch + 1] sub-row lengths -> offsets
     int *s_own = s_pre + kSpkBatch + 1;                // [tmax] this tile's spikes
+    int *s_seg = s_own + tmax;                         // [kEvChunk] owning spike of each event
 
     for (int q = l; q < 8 * kPoisMaxDev; q += nthr) s_thr[q] = B.pois_thr[q];
     for (int s = 0; s < R; ++s) {
@@ -602,10 +680,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                     }
                     pre = static_cast<int>(static_cast<uint32_t>(w));
                 }
-                const int64_t at = td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T + tl;
-                const uint32_t beg = P.sub_ptr[at];
-                s_beg[q] = static_cast<int>(beg);
-                s_pre[q] = static_cast<int>(P.sub_ptr[at + 1] - beg);
+                const uint2 sr = P.subrow[td.sub_base + (pre - td.inst_n0)];
+                s_beg[q] = static_cast<int>(sr.x);
+                s_pre[q] = static_cast<int>(sr.y);
             }
             __syncthreads();
             if (s_abort) break;
@@ -613,18 +690,26 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             lds_scan_excl(s_pre, nb, s_wave);
             const int E = s_pre[nb];
             ev_acc += static_cast<unsigned long long>(E);
-            for (int e = l; e < E; e += nthr) {
-                const int q = find_segment(s_pre, nb + 1, e);
+            auto deliver = [&](int e, int q) {
                 const uint32_t j = static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(e - s_pre[q]);
-                const int tg = B.tgt[j] - t0;
-                const int d = B.dly[j];
-                const int wq = weight_q8<WF>(B.w, j);
+                int tg, d;
+                const int wq = syn_record<SF>(P.syn, j, tg, d);
                 const int ds = static_cast<int>((n + d) & mask);
                 if (LRING)
                     atomicAdd(ring + ds * tmax + tg, wq);
                 else
                     __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            if (nb <= 32) {
+                for (int e = l; e < E; e += nthr) deliver(e, find_segment(s_pre, nb + 1, e));
+            } else {
+                for (int c0 = 0; c0 < E; c0 += kEvChunk) {
+                    const int cn = min(kEvChunk, E - c0);
+                    expand_segments(s_pre, nb, c0, cn, s_seg, s_wave);
+                    for (int x = l; x < cn; x += nthr) deliver(c0 + x, s_seg[x]);
+                    __syncthreads();
+                }
             }
             __syncthreads();
         }
@@ -660,52 +745,80 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     }
 }
 
-// Sub-row pointers of one instance: for each of its neurons i and local tile
-// tl, the first synapse of row i whose target is >= the tile's first neuron
-// (rows are sorted by target); the final entry is the end of the instance's
-// last row.
-__global__ void k_subrow_ptr(const uint64_t *row_ptr, const int32_t *tgt, const TileDesc *tiles, int itile0,
-                             int intiles, int32_t n0, int32_t nn, uint32_t *sub)
+// Sub-row table: entry (tile t, presynaptic neuron i of t's instance) = first
+// synapse and count of the part of row i whose targets lie in tile t (rows are
+// sorted by target, so that part is contiguous).
+__global__ void k_subrows(const uint64_t *row_ptr, const int32_t *tgt, const TileDesc *tiles, int n_tiles,
+                          int64_t entries, uint2 *subrow)
 {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t total = static_cast<int64_t>(nn) * intiles;
-    if (q > total) return;
-    if (q == total) {
-        sub[q] = static_cast<uint32_t>(row_ptr[n0 + nn]);
-        return;
+    if (q >= entries) return;
+    int lo = 0, hi = n_tiles;                      // tile whose row holds entry q
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tiles[mid].sub_base <= q) lo = mid; else hi = mid;
     }
-    const int32_t i = n0 + static_cast<int32_t>(q / intiles);
-    const int tl = static_cast<int>(q % intiles);
-    const int32_t key = tiles[itile0 + tl].t0;
-    uint64_t lo = row_ptr[i], hi = row_ptr[i + 1];
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (tgt[mid] < key) lo = mid + 1; else hi = mid;
+    const TileDesc td = tiles[lo];
+    const int32_t i = td.inst_n0 + static_cast<int32_t>(q - td.sub_base);
+    const int32_t k0 = td.t0, k1 = td.t0 + td.len;
+    uint64_t a = row_ptr[i], b = row_ptr[i + 1];
+    while (a < b) {
+        const uint64_t mid = (a + b) >> 1;
+        if (tgt[mid] < k0) a = mid + 1; else b = mid;
     }
-    sub[q] = static_cast<uint32_t>(lo);
+    uint64_t c = a, e = row_ptr[i + 1];
+    while (c < e) {
+        const uint64_t mid = (c + e) >> 1;
+        if (tgt[mid] < k1) c = mid + 1; else e = mid;
+    }
+    subrow[q] = make_uint2(static_cast<uint32_t>(a), static_cast<uint32_t>(c - a));
 }
 
-template <int WF, bool LR, int NPT>
+// Packed record of every synapse (grid-stride over the store).
+__global__ void k_pack_synapses(const int32_t *tgt, const uint8_t *dly, const void *w, int wfmt, const TileDesc *tiles,
+                                const int32_t *tile_of, int64_t m, int syn_fmt, void *syn)
+{
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < m;
+         j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t g = tgt[j];
+        const uint32_t local = static_cast<uint32_t>(g - tiles[tile_of[g]].t0);
+        const uint32_t d = dly[j];
+        uint32_t wbits = wfmt == 0 ? __float_as_uint(static_cast<const float *>(w)[j]) : static_cast<const uint16_t *>(w)[j];
+        if (syn_fmt <= kSyn8BF16) {
+            static_cast<uint2 *>(syn)[j] = make_uint2(local | (d << 16), wbits);
+        } else {
+            static_cast<uint32_t *>(syn)[j] = local | (d << 10) | (wbits << 16);
+        }
+    }
+}
+
+template <int SF, bool LR, int NPT>
 const void *tiled_fn3()
 {
-    return reinterpret_cast<const void *>(&k_tiled<WF, LR, NPT>);
+    return reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT>);
 }
 
-template <int WF, bool LR>
+template <int SF, bool LR>
 const void *tiled_fn2(int npt)
 {
-    return npt == 1 ? tiled_fn3<WF, LR, 1>() : npt == 2 ? tiled_fn3<WF, LR, 2>() : tiled_fn3<WF, LR, 4>();
+    return npt == 1 ? tiled_fn3<SF, LR, 1>() : npt == 2 ? tiled_fn3<SF, LR, 2>() : tiled_fn3<SF, LR, 4>();
 }
 
-template <int WF>
+template <int SF>
 const void *tiled_fn1(bool lr, int npt)
 {
-    return lr ? tiled_fn2<WF, true>(npt) : tiled_fn2<WF, false>(npt);
+    return lr ? tiled_fn2<SF, true>(npt) : tiled_fn2<SF, false>(npt);
 }
 
-const void *tiled_kernel(int wfmt, bool lr, int npt)
+const void *tiled_kernel(int sf, bool lr, int npt)
 {
-    return wfmt == 0 ? tiled_fn1<0>(lr, npt) : wfmt == 1 ? tiled_fn1<1>(lr, npt) : tiled_fn1<2>(lr, npt);
+    switch (sf) {
+    case kSyn8F32: return tiled_fn1<kSyn8F32>(lr, npt);
+    case kSyn8F16: return tiled_fn1<kSyn8F16>(lr, npt);
+    case kSyn8BF16: return tiled_fn1<kSyn8BF16>(lr, npt);
+    case kSyn4F16: return tiled_fn1<kSyn4F16>(lr, npt);
+    default: return tiled_fn1<kSyn4BF16>(lr, npt);
+    }
 }
 
 }  // namespace
@@ -718,25 +831,34 @@ TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring)
     const int per_thread = (tile_max + sh.npt - 1) / sh.npt;
     sh.threads = ((per_thread + 63) / 64) * 64;
     sh.lds = sizeof(int) * ((lds_ring ? static_cast<size_t>(ring) * tile_max : 0) + (2 * static_cast<size_t>(max_intiles) + 1) +
-                            3 * kSpkBatch + 1 + tile_max);
+                            3 * kSpkBatch + 1 + tile_max + kEvChunk);
     return sh;
 }
 
-hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_cu)
+hipError_t tiled_max_coresident(int syn_fmt, const TiledShape &sh, int *blocks_per_cu)
 {
-    const void *f = tiled_kernel(wfmt, sh.lds_ring, sh.npt);
+    const void *f = tiled_kernel(syn_fmt, sh.lds_ring, sh.npt);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, sh.threads, sh.lds);
 }
 
-hipError_t launch_subrow_ptr(const DevNet &d, const TileDesc *tiles_dev, int itile0, int intiles, int32_t n0,
-                             int32_t nn, uint32_t *sub, hipStream_t st)
+hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t entries, uint2 *subrow,
+                          hipStream_t st)
 {
-    const int64_t total = static_cast<int64_t>(nn) * intiles + 1;
-    const int64_t blocks = (total + 255) / 256;
-    hipLaunchKernelGGL(k_subrow_ptr, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d.row_ptr, d.tgt, tiles_dev,
-                       itile0, intiles, n0, nn, sub);
+    const int64_t blocks = (entries + 255) / 256;
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_subrows, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d.row_ptr, d.tgt, tiles_dev,
+                       n_tiles, entries, subrow);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, const int32_t *tile_of, int64_t m,
+                                int syn_fmt, void *syn, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_synapses, dim3(8192), dim3(256), 0, st, d.tgt, d.dly, d.w, d.wfmt, tiles_dev, tile_of, m,
+                       syn_fmt, syn);
     return hipGetLastError();
 }
 
@@ -745,7 +867,7 @@ hipError_t launch_tiled(const TiledNet &tn, const TiledShape &sh, int64_t steps,
     TiledNet arg = tn;
     int64_t nsteps = steps;
     void *args[] = {&arg, &nsteps};
-    return hipLaunchCooperativeKernel(tiled_kernel(tn.base.wfmt, sh.lds_ring, sh.npt), dim3(tn.n_tiles),
+    return hipLaunchCooperativeKernel(tiled_kernel(tn.syn_fmt, sh.lds_ring, sh.npt), dim3(tn.n_tiles),
                                       dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
 }
 
@@ -762,7 +884,7 @@ namespace {
 
 // One workgroup per tile: gather the tile's sub-rows of all listed neurons,
 // accumulate into an LDS copy of the tile's ring, then add it into the ring.
-template <int WF>
+template <int SF>
 __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t *ids, int32_t count, int64_t n)
 {
     extern __shared__ int lds[];
@@ -770,32 +892,36 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     const DevNet &B = P.base;
     const int t = blockIdx.x + P.pad0;                // tiles of one instance: offset in pad0
     const TileDesc td = P.tiles[t];
-    const int tl = t - td.itile0, T = td.intiles;
     const int l = threadIdx.x, nthr = blockDim.x;
     const int mask = B.ring_mask, R = mask + 1;
     const int tmax = P.tile_max, tlen = td.len;
     int *ring = lds;                                  // [R][tmax]
     int *s_beg = ring + R * tmax;                     // [kSpkBatch]
     int *s_pre = s_beg + kSpkBatch;                   // [kSpkBatch + 1]
+    int *s_seg = s_pre + kSpkBatch + 1;               // [kEvChunk]
     for (int q = l; q < R * tmax; q += nthr) ring[q] = 0;
     __syncthreads();
     for (int b0 = 0; b0 < count; b0 += kSpkBatch) {
         const int nb = min(kSpkBatch, count - b0);
         for (int q = l; q < nb; q += nthr) {
-            const int64_t at = td.sub_base + static_cast<int64_t>(ids[b0 + q] - td.inst_n0) * T + tl;
-            const uint32_t beg = P.sub_ptr[at];
-            s_beg[q] = static_cast<int>(beg);
-            s_pre[q] = static_cast<int>(P.sub_ptr[at + 1] - beg);
+            const uint2 sr = P.subrow[td.sub_base + (ids[b0 + q] - td.inst_n0)];
+            s_beg[q] = static_cast<int>(sr.x);
+            s_pre[q] = static_cast<int>(sr.y);
         }
         __syncthreads();
         lds_scan_excl(s_pre, nb, s_wave);
         const int E = s_pre[nb];
-        for (int e = l; e < E; e += nthr) {
-            const int q = find_segment(s_pre, nb + 1, e);
-            const uint32_t j = static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(e - s_pre[q]);
-            const int tg = B.tgt[j] - td.t0;
-            const int d = B.dly[j];
-            atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, weight_q8<WF>(B.w, j));
+        for (int c0 = 0; c0 < E; c0 += kEvChunk) {
+            const int cn = min(kEvChunk, E - c0);
+            expand_segments(s_pre, nb, c0, cn, s_seg, s_wave);
+            for (int x = l; x < cn; x += nthr) {
+                const int q = s_seg[x];
+                const uint32_t j = static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(c0 + x - s_pre[q]);
+                int tg, d;
+                const int wq = syn_record<SF>(P.syn, j, tg, d);
+                atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, wq);
+            }
+            __syncthreads();
         }
         __syncthreads();
     }
@@ -823,14 +949,14 @@ __global__ __launch_bounds__(256) void k_inject_global(DevNet P, const int32_t *
     }
 }
 
-template <int WF>
-const void *inject_tiled_fn() { return reinterpret_cast<const void *>(&k_inject_tiled<WF>); }
+template <int SF>
+const void *inject_tiled_fn() { return reinterpret_cast<const void *>(&k_inject_tiled<SF>); }
 
 }  // namespace
 
 size_t inject_lds_bytes(int tile_max, int ring)
 {
-    return sizeof(int) * (static_cast<size_t>(ring) * tile_max + 2 * kSpkBatch + 1);
+    return sizeof(int) * (static_cast<size_t>(ring) * tile_max + 2 * kSpkBatch + 1 + kEvChunk);
 }
 
 hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
@@ -839,7 +965,10 @@ hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, i
     TiledNet arg = tn;
     arg.pad0 = first_tile;
     const size_t lds = inject_lds_bytes(tn.tile_max, tn.base.ring_mask + 1);
-    const void *f = tn.base.wfmt == 0 ? inject_tiled_fn<0>() : tn.base.wfmt == 1 ? inject_tiled_fn<1>() : inject_tiled_fn<2>();
+    const void *f = tn.syn_fmt == kSyn8F32 ? inject_tiled_fn<kSyn8F32>()
+                  : tn.syn_fmt == kSyn8F16 ? inject_tiled_fn<kSyn8F16>()
+                  : tn.syn_fmt == kSyn8BF16 ? inject_tiled_fn<kSyn8BF16>()
+                  : tn.syn_fmt == kSyn4F16 ? inject_tiled_fn<kSyn4F16>() : inject_tiled_fn<kSyn4BF16>();
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
     void *args[] = {&arg, const_cast<int32_t **>(&ids), &count, &n};

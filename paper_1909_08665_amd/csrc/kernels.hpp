@@ -65,8 +65,16 @@ struct TileDesc {
     int32_t intiles;                  // number of tiles of the instance
     int32_t inst_n0;                  // first neuron of the instance
     int32_t pad;
-    int64_t sub_base;                 // sub_ptr index of (first neuron of the instance, local tile 0)
+    int64_t sub_base;                 // index in `subrow` of this tile's row (one entry per neuron of its instance)
 };
+
+// Packed synapse records of the tiled engine, in CSR order (so a sub-row is a
+// contiguous index range): tile-local target, delay, weight.
+//   0: 8 B {u16 target | u8 delay | u8 0, f32 weight}
+//   1: 8 B {same, FP16 weight bits}          2: 8 B {same, BF16 weight bits}
+//   3: 4 B {10-bit target | 6-bit delay | FP16 weight}   (tile <= 1024, R <= 64)
+//   4: 4 B {10-bit target | 6-bit delay | BF16 weight}
+enum SynFmt : int32_t { kSyn8F32 = 0, kSyn8F16 = 1, kSyn8BF16 = 2, kSyn4F16 = 3, kSyn4BF16 = 4 };
 
 struct TiledNet {
     DevNet base;
@@ -75,7 +83,11 @@ struct TiledNet {
     int32_t max_intiles;              // most tiles of one instance
     int32_t pad0;
     const TileDesc *tiles;            // [n_tiles]
-    const uint32_t *sub_ptr;          // per instance j: [N_j * T_j + 1] first synapse of (pre, local tile)
+    const uint2 *subrow;              // per tile: [neurons of its instance] (first synapse, count) of the
+                                      // sub-row of that presynaptic neuron that targets the tile
+    const void *syn;                  // packed synapse records (SynFmt), CSR order
+    int32_t syn_fmt;
+    int32_t pad2;
     uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first id)
     uint64_t *xent;                   // [2][n_tiles][tile_max] further spike ids (tag32 | id)
     uint32_t *abort;                  // set when a wait gives up
@@ -112,7 +124,11 @@ size_t inject_lds_bytes(int tile_max, int ring);
 hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
                                int32_t count, int64_t n, hipStream_t st);
 hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int64_t n, hipStream_t st);
-hipError_t launch_subrow_ptr(const DevNet &d, const TileDesc *tiles_dev, int itile0, int intiles, int32_t n0,
-                             int32_t n_inst_neurons, uint32_t *sub_ptr_inst, hipStream_t st);
+// Device-side construction of the tiled engine's sub-row table and packed
+// synapse store (rows sorted by target; tile_of: tile index of every neuron).
+hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t entries, uint2 *subrow,
+                          hipStream_t st);
+hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, const int32_t *tile_of, int64_t m,
+                                int syn_fmt, void *syn, hipStream_t st);
 
 }  // namespace mc
