@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--engine", choices=["auto", "graph", "tiled"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--poll-delay", type=int, default=0,
+                    help="tiled engine: sleep before polling, units of 64 clocks (-1 none, 0 library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-warm", type=int, default=1000)
     ap.add_argument("--cpu-steps", type=int, default=5000)
@@ -197,6 +199,8 @@ def main():
         net = mc.Network.build_batch(seeds, scales, conn, wfmt=WFMT[args.wfmt], engine=engine)
     if args.tile:
         net.set_launch(engine=mc.ENGINE_TILED, tile=args.tile)
+    if args.poll_delay:
+        net.set_launch(poll_delay=args.poll_delay)
     info = net.info()
     n_neurons, n_syn = info["n_neurons"], info["n_synapses"]
     log(f"build+upload {time.time() - t:.1f}s: {n_inst} instance(s), {n_neurons} neurons, {n_syn} synapses")
@@ -279,7 +283,8 @@ def main():
                    "instances": n_inst, "seed": seeds[0] if n_inst == 1 else [seeds[0], seeds[-1]],
                    "conn_table": standin_description(),
                    "engine": "tiled" if tiled else "graph", "tile": info["tile_neurons"],
-                   "n_tiles": info["n_tiles"], "ring_depth": info["ring_depth"]},
+                   "n_tiles": info["n_tiles"], "ring_depth": info["ring_depth"],
+                   "poll_delay": info["poll_delay"] if tiled else None},
         "events_per_s": round(events / wall, 1),
         "spikes_per_step": round(spikes / args.steps, 3),
         "max_spikes_per_step": c1["max_spikes_per_step"],

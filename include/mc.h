@@ -125,6 +125,8 @@ typedef struct mc_info {
     int32_t syn_bytes;           /* bytes read per delivered synapse by the engine in use:
                                     GRAPH 9 (FP32) / 7 (FP16, BF16) from the CSR arrays;
                                     TILED 8, or 4 for FP16/BF16 tiles of <= 1024 neurons */
+    int32_t poll_delay;          /* TILED engine: sleep before a step's first poll of the
+                                    other tiles' words, units of 64 clocks */
 } mc_info;
 
 /* Launch knobs chosen by the autotuner or set by hand (0 = keep current). */
@@ -137,6 +139,9 @@ typedef struct mc_launch {
     int32_t seg;                 /* 64, 128, 256 or 512 */
     int32_t block;               /* 64, 128, 256 or 512 */
     int32_t deliver_grid;        /* >= 1 */
+    int32_t poll_delay;          /* TILED engine: sleep before a step's first poll of the other
+                                    tiles' words, in units of 64 clocks, 1..255; -1 for none.
+                                    Speed only: results do not depend on it. */
 } mc_launch;
 
 /* Fill *cfg with the defaults of Sec. 2a; conn_probs is left NULL. */

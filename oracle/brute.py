@@ -123,7 +123,11 @@ class BruteNet:
         self.spikes = []
 
     def poisson(self, n, i):
-        v = philox4x64_10((n, i, 0, 2), (self.seed, 0))[0] >> 32
+        """Count for neuron i at step n: 32-bit half i mod 8 of the block
+        (n, i // 8, 0, 2), halves taken high then low of each 64-bit word."""
+        block = philox4x64_10((n, i // 8, 0, 2), (self.seed, 0))
+        halves = [h for w in block for h in (w >> 32, w & 0xFFFFFFFF)]
+        v = halves[i % 8]
         return sum(1 for t in self.thr[self.pop_of[i]] if v >= t)
 
     def run(self, steps):

@@ -42,8 +42,10 @@
  *      a 32-bit uniform against K_MAX fixed-point CDF thresholds.
  *   R8 Initial state: u ~ U[0, theta), I = 0, not refractory.
  *   R9 Random numbers: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
- *      counter (c0, c1, c2, tag) -- one block per synapse, per neuron-step
- *      Poisson draw and per neuron initial value.
+ *      counter (c0, c1, c2, tag) -- one block per synapse and per neuron initial
+ *      value; one block per step and group of 8 consecutive neurons for the
+ *      Poisson draws, neuron i taking 32-bit half (i mod 8) of the 256 bits
+ *      (halves ordered high, low of word 0, then of words 1, 2, 3).
  *   R10 FP32 mirror: every product and sum rounded to float, no fused multiply-add;
  *      synaptic input accumulated as int32 in units of 1/256 pA (Q8), converted to
  *      float with round-to-nearest-even and scaled by 2^-8 (exact).
@@ -503,9 +505,11 @@ or_net *or_build_explicit(const or_params *p, uint64_t seed, const int32_t *pop_
 /* ------------------------------------------------------------------------- */
 static int poisson_count(const or_net *nt, int pop, int64_t n, int32_t i)
 {
-    uint64_t c[4] = {(uint64_t)n, (uint64_t)i, 0, TAG_POIS}, k[2] = {nt->seed, nt->p.pois_stream}, x[4];
+    uint64_t c[4] = {(uint64_t)n, (uint64_t)(i / 8), 0, TAG_POIS}, k[2] = {nt->seed, nt->p.pois_stream}, x[4];
     or_philox(c, k, x);
-    uint64_t v = x[0] >> 32;
+    const int h = i % 8;
+    const uint64_t word = x[h / 2];
+    uint64_t v = (h % 2 == 0) ? (word >> 32) : (word & 0xFFFFFFFFULL);
     int cnt = 0;
     for (int j = 0; j < OR_KMAX; ++j)
         if (v >= nt->T[pop][j]) cnt++;

@@ -49,12 +49,13 @@ class McInfo(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("ring_depth", C.c_int32), ("engine", C.c_int32), ("wfmt", C.c_int32),
                 ("n_neurons", C.c_int64), ("n_synapses", C.c_int64), ("tile_neurons", C.c_int32),
                 ("n_tiles", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
-                ("deliver_grid", C.c_int32), ("lds_ring", C.c_int32), ("syn_bytes", C.c_int32)]
+                ("deliver_grid", C.c_int32), ("lds_ring", C.c_int32), ("syn_bytes", C.c_int32),
+                ("poll_delay", C.c_int32)]
 
 
 class McLaunch(C.Structure):
     _fields_ = [("engine", C.c_int32), ("tile", C.c_int32), ("ring", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
-                ("deliver_grid", C.c_int32)]
+                ("deliver_grid", C.c_int32), ("poll_delay", C.c_int32)]
 
 
 # Every entry point declared in include/mc.h.
@@ -188,9 +189,11 @@ class Network:
     def run(self, steps):
         _check(lib().mc_run(self._h, int(steps)))
 
-    def set_launch(self, engine=0, tile=0, ring=0, graph_chunk=0, seg=0, block=0, deliver_grid=0):
-        """ring: 0 auto, 1 tile ring in LDS, 2 tile ring in global memory (tiled engine)."""
-        l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid)
+    def set_launch(self, engine=0, tile=0, ring=0, graph_chunk=0, seg=0, block=0, deliver_grid=0, poll_delay=0):
+        """ring: 0 auto, 1 tile ring in LDS, 2 tile ring in global memory (tiled engine).
+        poll_delay: tiled engine, sleep before polling in units of 64 clocks (-1 none).
+        0 keeps the current value of any knob."""
+        l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid, poll_delay)
         _check(lib().mc_set_launch(self._h, C.byref(l)))
 
     def tune(self, trial_steps=200):

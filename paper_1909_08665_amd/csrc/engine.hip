@@ -42,6 +42,10 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 constexpr int64_t kSegMin = 100, kSegMax = 10000;   // steps between recorder drains
+// Tiled engine: sleep before a step's first poll, in units of 64 clocks, when
+// the instances have at least kPollDelayTiles tiles (T tiles each polling T
+// words congest the lines the last stores go to); none for fewer tiles.
+constexpr int kPollDelayDefault = 32, kPollDelayTiles = 64;
 
 }  // namespace
 
@@ -77,6 +81,13 @@ struct mc_net {
     // pinned staging for recorder drains
     int32_t *h_rec_id = nullptr, *h_rec_step = nullptr;
     mc::StepCtl *h_ctl = nullptr;
+    // Second recorder, pinned copies and counter snapshot: the tiled engine
+    // alternates recorders between segments and drains one while the next runs.
+    int32_t *rec_id1 = nullptr, *rec_step1 = nullptr;
+    int32_t *h_rec_id1 = nullptr, *h_rec_step1 = nullptr;
+    mc::StepCtl *h_ctl1 = nullptr;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t seg_ev0[2] = {}, seg_ev1[2] = {}, snap_ev[2] = {};
 
     // tiled engine
     int tile = 0, n_tiles = 0, tile_max = 0, max_intiles = 0;
@@ -90,7 +101,9 @@ struct mc_net {
     uint2 *subrow = nullptr;           // tiled engine: per-tile (first synapse, count) of each sub-row
     void *syn = nullptr;               // tiled engine: packed synapse records
     int32_t syn_fmt = 0;
-    uint64_t *xchg = nullptr, *xent = nullptr;
+    uint32_t *xchg = nullptr;
+    uint64_t *xent = nullptr;
+    int64_t xent_high = 0;            // entry words may carry tags of steps below this
     uint32_t *abort_flag = nullptr;
     uint64_t *trace = nullptr;
     int32_t trace_steps = 0;
@@ -105,6 +118,8 @@ struct mc_net {
     int seg = 256;
     int block = 256;
     int deliver_grid = 1024;
+    int poll_delay = 0;
+    bool poll_delay_set = false;      // chosen by mc_set_launch or the tuner; otherwise by tile count
     hipGraphExec_t graph_exec = nullptr;
     int graph_k = 0;
 
@@ -178,14 +193,19 @@ void release(mc_net *nt)
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
                     nt->rec_id, nt->rec_step, nt->subrow, nt->syn, nt->xchg, nt->xent, nt->abort_flag, nt->trace,
-                    nt->tiles_dev, nt->gring, nt->inject_buf};
+                    nt->tiles_dev, nt->gring, nt->inject_buf, nt->rec_id1, nt->rec_step1};
     for (void *b : bufs)
         if (b) hipFree(b);
-    if (nt->h_rec_id) hipHostFree(nt->h_rec_id);
-    if (nt->h_rec_step) hipHostFree(nt->h_rec_step);
-    if (nt->h_ctl) hipHostFree(nt->h_ctl);
+    for (void *b : {static_cast<void *>(nt->h_rec_id), static_cast<void *>(nt->h_rec_step), static_cast<void *>(nt->h_ctl),
+                    static_cast<void *>(nt->h_rec_id1), static_cast<void *>(nt->h_rec_step1),
+                    static_cast<void *>(nt->h_ctl1)})
+        if (b) hipHostFree(b);
     if (nt->ev0) hipEventDestroy(nt->ev0);
     if (nt->ev1) hipEventDestroy(nt->ev1);
+    for (int b = 0; b < 2; ++b)
+        for (hipEvent_t e : {nt->seg_ev0[b], nt->seg_ev1[b], nt->snap_ev[b]})
+            if (e) hipEventDestroy(e);
+    if (nt->copy_stream) hipStreamDestroy(nt->copy_stream);
     if (nt->stream && nt->own_stream) hipStreamDestroy(nt->stream);
     delete nt;
 }
@@ -244,6 +264,12 @@ int upload(mc_net *nt, const mc_config *cfg)
     nt->own_stream = true;
     HIP_TRY(hipEventCreate(&nt->ev0));
     HIP_TRY(hipEventCreate(&nt->ev1));
+    HIP_TRY(hipStreamCreateWithFlags(&nt->copy_stream, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipEventCreate(&nt->seg_ev0[b]));
+        HIP_TRY(hipEventCreate(&nt->seg_ev1[b]));
+        HIP_TRY(hipEventCreateWithFlags(&nt->snap_ev[b], hipEventDisableTiming));
+    }
 
     if ((rc = dalloc(&nt->u, N)) || (rc = dalloc(&nt->cur, N)) || (rc = dalloc(&nt->refr, N)) ||
         (rc = dalloc(&nt->meta, N)) || (rc = dalloc(&nt->inst_off, H.n_inst + 1)) ||
@@ -264,10 +290,15 @@ int upload(mc_net *nt, const mc_config *cfg)
     int64_t cap = cfg->record_capacity;
     if (cap <= 0) cap = std::max<int64_t>(int64_t{1} << 22, 64 * N);
     nt->rec_cap = cap;
-    if ((rc = dalloc(&nt->rec_id, cap)) || (rc = dalloc(&nt->rec_step, cap))) return rc;
+    if ((rc = dalloc(&nt->rec_id, cap)) || (rc = dalloc(&nt->rec_step, cap)) || (rc = dalloc(&nt->rec_id1, cap)) ||
+        (rc = dalloc(&nt->rec_step1, cap)))
+        return rc;
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_id), cap * sizeof(int32_t), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_step), cap * sizeof(int32_t), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl), sizeof(mc::StepCtl), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_id1), cap * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_step1), cap * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl1), sizeof(mc::StepCtl), hipHostMallocDefault));
 
     // Static data.
     HIP_TRY(hipMemcpy(nt->meta, H.meta.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -326,6 +357,7 @@ void plan_tiles(const mc_net *nt, int target, std::vector<mc::TileDesc> &tiles, 
             d.itile0 = first;
             d.intiles = T;
             d.inst_n0 = n0;
+            d.stride = len;
             d.sub_base = sub_total;              // this tile's row: one entry per neuron of the instance
             tiles.push_back(d);
             tile_max = std::max(tile_max, d.len);
@@ -393,6 +425,7 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     }
     HIP_TRY(hipMemcpy(nt->tiles_dev, tiles.data(), T * sizeof(mc::TileDesc), hipMemcpyHostToDevice));
     HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * T * tile_max * sizeof(uint64_t), nt->stream));
+    nt->xent_high = 0;
     {
         const size_t rec = sf <= mc::kSyn8BF16 ? 8 : 4;
         hipError_t e = hipMalloc(&nt->syn, std::max<size_t>(1, static_cast<size_t>(nt->host.m) * rec));
@@ -418,6 +451,7 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     nt->n_tiles = T;
     nt->tile_max = tile_max;
     nt->max_intiles = max_intiles;
+    if (!nt->poll_delay_set) nt->poll_delay = max_intiles >= kPollDelayTiles ? kPollDelayDefault : 0;
     nt->tiled_shape = sh;
     return MC_OK;
 }
@@ -501,33 +535,23 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
 }
 
 
-// Copy the recorder to the host, reset it, check error flags.
-int drain(mc_net *nt)
+// Fold the spikes of the steps [s0, s0 + span) that a recorder holds (counter
+// snapshot c, host copies ids/steps) into the per-instance record and counters,
+// and check the error flags.
+int absorb(mc_net *nt, const mc::StepCtl &c, const int32_t *rec_ids, const int32_t *rec_steps, int64_t s0,
+           int64_t span)
 {
-    HIP_TRY(hipMemcpyAsync(nt->h_ctl, nt->ctl, sizeof(mc::StepCtl), hipMemcpyDeviceToHost, nt->stream));
-    HIP_TRY(hipStreamSynchronize(nt->stream));
-    const int64_t total = nt->h_ctl->rec_total;
+    const int64_t total = c.rec_total;
     const int64_t got = std::min(total, nt->rec_cap);
-    if (got > 0) {
-        HIP_TRY(hipMemcpyAsync(nt->h_rec_id, nt->rec_id, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
-        HIP_TRY(hipMemcpyAsync(nt->h_rec_step, nt->rec_step, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
-    }
-    const int64_t zero = 0;
-    const uint32_t zflags = 0;
-    HIP_TRY(hipMemcpyAsync(&nt->ctl->rec_total, &zero, sizeof(zero), hipMemcpyHostToDevice, nt->stream));
-    HIP_TRY(hipMemcpyAsync(&nt->ctl->flags, &zflags, sizeof(zflags), hipMemcpyHostToDevice, nt->stream));
-    HIP_TRY(hipStreamSynchronize(nt->stream));
     const auto &rp = nt->host.row_ptr;
-    // spikes per step, whole network and per instance, for the largest-step counters
-    const int64_t s0 = nt->step;
-    const int64_t span = std::max<int64_t>(1, nt->steps_in_flight);
+    span = std::max<int64_t>(1, span);
     std::vector<int32_t> per_step(static_cast<size_t>(span), 0);
     std::vector<int32_t> per_inst_step;
     if (nt->host.n_inst > 1) per_inst_step.assign(static_cast<size_t>(span) * nt->host.n_inst, 0);
     for (int64_t q = 0; q < got; ++q) {
-        const int32_t gid = nt->h_rec_id[q];
+        const int32_t gid = rec_ids[q];
         const int inst = static_cast<int>(nt->host.meta[gid] >> 3);
-        const int64_t st = nt->h_rec_step[q];
+        const int64_t st = rec_steps[q];
         nt->unread[inst].emplace_back(st, gid - nt->host.inst_off[inst]);
         nt->inst_spikes[inst] += 1;
         nt->inst_events[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
@@ -544,9 +568,25 @@ int drain(mc_net *nt)
             for (int j = 0; j < nt->host.n_inst; ++j)
                 nt->inst_max_step[j] = std::max<int64_t>(nt->inst_max_step[j], per_inst_step[static_cast<size_t>(k) * nt->host.n_inst + j]);
     }
-    if (total > nt->rec_cap || (nt->h_ctl->flags & mc::kFlagRecordOverflow)) nt->overflow = true;
-    if (nt->h_ctl->flags & mc::kFlagTimeout) return fail(MC_ERR_HIP, "a cross-tile wait timed out");
+    if (total > nt->rec_cap || (c.flags & mc::kFlagRecordOverflow)) nt->overflow = true;
+    if (c.flags & mc::kFlagTimeout) return fail(MC_ERR_HIP, "a cross-tile wait timed out");
     return MC_OK;
+}
+
+// Copy the recorder to the host, reset it, fold it in (the serial form).
+int drain(mc_net *nt)
+{
+    HIP_TRY(hipMemcpyAsync(nt->h_ctl, nt->ctl, sizeof(mc::StepCtl), hipMemcpyDeviceToHost, nt->stream));
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    const int64_t got = std::min(nt->h_ctl->rec_total, nt->rec_cap);
+    if (got > 0) {
+        HIP_TRY(hipMemcpyAsync(nt->h_rec_id, nt->rec_id, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
+        HIP_TRY(hipMemcpyAsync(nt->h_rec_step, nt->rec_step, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
+    }
+    HIP_TRY(hipMemsetAsync(&nt->ctl->rec_total, 0, sizeof(int64_t), nt->stream));
+    HIP_TRY(hipMemsetAsync(&nt->ctl->flags, 0, sizeof(uint32_t), nt->stream));
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    return absorb(nt, *nt->h_ctl, nt->h_rec_id, nt->h_rec_step, nt->step, nt->steps_in_flight);
 }
 
 // Steps until the next drain: keep the recorder at most a quarter full at the
@@ -572,39 +612,88 @@ int run_tiled(mc_net *nt, int64_t steps)
     tn.syn = nt->syn;
     tn.syn_fmt = nt->syn_fmt;
     tn.xchg = nt->xchg;
+    tn.poll_delay = nt->poll_delay;
     tn.xent = nt->xent;
     tn.abort = nt->abort_flag;
+    // Entry words are tagged with their step.  After the step index went back
+    // (checkpoint load, autotuner roll-back) the buffer may hold words of the
+    // abandoned steps with the very tags about to be polled: clear it.
+    if (nt->step < nt->xent_high)
+        HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * nt->n_tiles * nt->tile_max * sizeof(uint64_t),
+                               nt->stream));
+    // Segments alternate between the two recorders.  After enqueueing segment k
+    // (kernel, then a copy of its counters into pinned memory) the host drains
+    // segment k-1 -- copy on the copy stream, fold into the record -- while
+    // segment k runs.
+    struct Pending {
+        int64_t s0, len;
+        int buf;
+    };
+    Pending pend{0, 0, -1};
+    int buf = 0;
+    const bool timing = nt->timing;
+    auto finish = [nt, timing](const Pending &p) -> int {
+        HIP_TRY(hipEventSynchronize(nt->snap_ev[p.buf]));
+        const mc::StepCtl &c = p.buf ? *nt->h_ctl1 : *nt->h_ctl;
+        int32_t *h_ids = p.buf ? nt->h_rec_id1 : nt->h_rec_id, *h_steps = p.buf ? nt->h_rec_step1 : nt->h_rec_step;
+        const int64_t got = std::min(c.rec_total, nt->rec_cap);
+        if (got > 0) {
+            HIP_TRY(hipMemcpyAsync(h_ids, p.buf ? nt->rec_id1 : nt->rec_id, got * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   nt->copy_stream));
+            HIP_TRY(hipMemcpyAsync(h_steps, p.buf ? nt->rec_step1 : nt->rec_step, got * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, nt->copy_stream));
+            HIP_TRY(hipStreamSynchronize(nt->copy_stream));
+        }
+        if (timing) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, nt->seg_ev0[p.buf], nt->seg_ev1[p.buf]));
+            nt->kernel_ms += ms;
+            nt->launches += 1;
+        }
+        const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
+        const int rc = absorb(nt, c, h_ids, h_steps, p.s0, p.len);
+        const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
+        adapt_segment(nt, p.len, after - before);
+        return rc;
+    };
     bool first = true;
-    while (steps > 0) {
+    int rc = MC_OK;
+    while (steps > 0 && rc == MC_OK) {
         // the phase trace covers the first steps of the first launch of this run
         tn.trace = first && nt->trace_tiles == nt->n_tiles ? nt->trace : nullptr;
         tn.trace_steps = nt->trace_steps;
         first = false;
         const int64_t seg = std::min(steps, nt->seg_steps);
+        nt->xent_high = std::max(nt->xent_high, nt->step + seg);
+        tn.base.rec_id = buf ? nt->rec_id1 : nt->rec_id;
+        tn.base.rec_step = buf ? nt->rec_step1 : nt->rec_step;
         // Tile words from an earlier launch carry older tags; clearing them rules out
         // a tag match across a jump of the step index (engine switch).
-        HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint64_t), nt->stream));
+        HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint32_t), nt->stream));
         HIP_TRY(hipMemsetAsync(nt->abort_flag, 0, sizeof(uint32_t), nt->stream));
-        if (nt->timing) HIP_TRY(hipEventRecord(nt->ev0, nt->stream));
+        HIP_TRY(hipMemsetAsync(&nt->ctl->rec_total, 0, sizeof(int64_t), nt->stream));
+        HIP_TRY(hipMemsetAsync(&nt->ctl->flags, 0, sizeof(uint32_t), nt->stream));
+        if (timing) HIP_TRY(hipEventRecord(nt->seg_ev0[buf], nt->stream));
         HIP_TRY(mc::launch_tiled(tn, nt->tiled_shape, seg, nt->stream));
-        if (nt->timing) {
-            HIP_TRY(hipEventRecord(nt->ev1, nt->stream));
-            HIP_TRY(hipEventSynchronize(nt->ev1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, nt->ev0, nt->ev1));
-            nt->kernel_ms += ms;
-            nt->launches += 1;
-        }
-        const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
-        nt->steps_in_flight = seg;
-        int rc = drain(nt);
-        if (rc) return rc;
-        const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
-        adapt_segment(nt, seg, after - before);
+        if (timing) HIP_TRY(hipEventRecord(nt->seg_ev1[buf], nt->stream));
+        HIP_TRY(hipMemcpyAsync(buf ? nt->h_ctl1 : nt->h_ctl, nt->ctl, sizeof(mc::StepCtl), hipMemcpyDeviceToHost,
+                               nt->stream));
+        HIP_TRY(hipEventRecord(nt->snap_ev[buf], nt->stream));
+        if (pend.buf >= 0) rc = finish(pend);
+        pend = {nt->step, seg, buf};
+        buf ^= 1;
         nt->step += seg;
         steps -= seg;
     }
-    return MC_OK;
+    if (pend.buf >= 0) {
+        const int rc2 = finish(pend);
+        if (rc == MC_OK) rc = rc2;
+    }
+    // leave the counters at rest for the other engine and for snapshots
+    HIP_TRY(hipMemsetAsync(&nt->ctl->rec_total, 0, sizeof(int64_t), nt->stream));
+    HIP_TRY(hipMemsetAsync(&nt->ctl->flags, 0, sizeof(uint32_t), nt->stream));
+    HIP_TRY(hipStreamSynchronize(nt->stream));
+    return rc;
 }
 
 int ensure_graph(mc_net *nt)
@@ -814,6 +903,7 @@ int run_engine(mc_net *nt, int64_t steps)
 // A launch configuration the tuner can select.
 struct Candidate {
     int engine, tile, ring, graph_chunk, seg, block, grid;
+    int poll;                         // tiled: poll delay, or -1 for the default of the tile count
 };
 
 int apply_candidate(mc_net *nt, const Candidate &c)
@@ -822,6 +912,8 @@ int apply_candidate(mc_net *nt, const Candidate &c)
         const int rc = setup_tiled(nt, c.tile, c.ring);
         if (rc) return rc;
         nt->engine = MC_ENGINE_TILED;
+        nt->poll_delay_set = c.poll >= 0;
+        nt->poll_delay = c.poll >= 0 ? c.poll : (nt->max_intiles >= kPollDelayTiles ? kPollDelayDefault : 0);
         return MC_OK;
     }
     if (nt->graph_chunk != c.graph_chunk || nt->seg != c.seg || nt->block != c.block || nt->deliver_grid != c.grid) {
@@ -857,28 +949,41 @@ int autotune(mc_net *nt, int64_t trial_steps)
         for (int per_cu : {1, 2, 3, 4}) {
             const int64_t cap = static_cast<int64_t>(cus) * per_cu;
             const int64_t tile = fitting_tile(nt, cap, std::max<int64_t>(64, (N + cap - 1) / cap));
-            if (tile <= 4096) cands.push_back({MC_ENGINE_TILED, static_cast<int>(tile), ring, 0, 0, 0, 0});
+            if (tile <= 4096) cands.push_back({MC_ENGINE_TILED, static_cast<int>(tile), ring, 0, 0, 0, 0, -1});
         }
     for (int block : {128, 256, 512})
         for (int seg : {128, 256, 512})
             for (int grid : {512, 2048})
                 for (int chunk : {32, 128})
-                    cands.push_back({MC_ENGINE_GRAPH, 0, 0, chunk, seg, block, grid});
+                    cands.push_back({MC_ENGINE_GRAPH, 0, 0, chunk, seg, block, grid, 0});
     double best = 1e300;
     Candidate pick{nt->engine, nt->tile, nt->tiled_shape.lds_ring ? 1 : 2, nt->graph_chunk, nt->seg, nt->block,
-                   nt->deliver_grid};
-    for (const Candidate &c : cands) {
-        if (apply_candidate(nt, c) != MC_OK) continue;       // e.g. the tile ring does not fit in LDS
-        if ((rc = restore_snapshot(nt, s))) return rc;
+                   nt->deliver_grid, nt->poll_delay_set ? nt->poll_delay : -1};
+    auto trial = [&](const Candidate &c) -> int {
+        if (apply_candidate(nt, c) != MC_OK) return MC_OK;   // e.g. the tile ring does not fit in LDS
+        int r;
+        if ((r = restore_snapshot(nt, s))) return r;
         nt->seg_steps = std::max<int64_t>(trial_steps, 1);
-        if ((rc = run_engine(nt, std::max<int64_t>(8, trial_steps / 8)))) return rc;   // graph capture, warm caches
-        if ((rc = restore_snapshot(nt, s))) return rc;
+        if ((r = run_engine(nt, std::max<int64_t>(8, trial_steps / 8)))) return r;   // graph capture, warm caches
+        if ((r = restore_snapshot(nt, s))) return r;
         const auto t0 = std::chrono::steady_clock::now();
-        if ((rc = run_engine(nt, trial_steps))) return rc;
+        if ((r = run_engine(nt, trial_steps))) return r;
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (dt < best) {
             best = dt;
             pick = c;
+        }
+        return MC_OK;
+    };
+    for (const Candidate &c : cands)
+        if ((rc = trial(c))) return rc;
+    // then the tiled engine's polling delay for the chosen tiles
+    if (pick.engine == MC_ENGINE_TILED) {
+        const Candidate base = pick;
+        for (int d : {0, 8, 16, 24, 32, 48, 64}) {
+            Candidate c = base;
+            c.poll = d;
+            if ((rc = trial(c))) return rc;
         }
     }
     g_err.clear();
@@ -1065,6 +1170,7 @@ int mc_get_info(mc_net *net, mc_info *out)
     out->seg = net->seg;
     out->block = net->block;
     out->deliver_grid = net->deliver_grid;
+    out->poll_delay = net->poll_delay;
     return MC_OK;
 }
 
@@ -1113,6 +1219,11 @@ int mc_set_launch(mc_net *net, const mc_launch *l)
     if (l->seg && l->seg != 64 && l->seg != 128 && l->seg != 256 && l->seg != 512) return fail(MC_ERR_ARG, "seg must be 64, 128, 256 or 512");
     if (l->block && l->block != 64 && l->block != 128 && l->block != 256 && l->block != 512) return fail(MC_ERR_ARG, "block must be 64, 128, 256 or 512");
     if (l->deliver_grid < 0) return fail(MC_ERR_ARG, "deliver_grid must be >= 1");
+    if (l->poll_delay < -1 || l->poll_delay > 255) return fail(MC_ERR_ARG, "poll_delay must be -1 or in [1, 255]");
+    if (l->poll_delay) {
+        net->poll_delay = l->poll_delay < 0 ? 0 : l->poll_delay;
+        net->poll_delay_set = true;
+    }
     bool changed = false;
     auto set = [&changed](int &dst, int v) { if (v && dst != v) { dst = v; changed = true; } };
     set(net->graph_chunk, l->graph_chunk);

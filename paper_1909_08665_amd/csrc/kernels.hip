@@ -24,8 +24,8 @@ namespace {
 constexpr uint64_t kMulA = 0xD2E7470EE14C6C93ULL, kMulB = 0xCA5A826395121157ULL;
 constexpr uint64_t kBumpA = 0x9E3779B97F4A7C15ULL, kBumpB = 0xBB67AE8584CAA73BULL;
 
-// First output word of Philox4x64-10 for counter (c0, c1, 0, tag), key (seed, 0).
-__device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t c1, uint64_t tag, uint64_t seed)
+// Philox4x64-10 block for counter (c0, c1, 0, tag), key (seed, 0).
+__device__ __forceinline__ void philox_block(uint64_t c0, uint64_t c1, uint64_t tag, uint64_t seed, uint64_t out[4])
 {
     uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = tag;
     uint64_t k0 = seed, k1 = 0;
@@ -38,17 +38,38 @@ __device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t c1, uint6
         x0 = y0; x1 = b_lo; x2 = y2; x3 = a_lo;
         k0 += kBumpA; k1 += kBumpB;
     }
-    return x0;
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-// Background spikes of neuron `local` at step n: the number of CDF thresholds
-// not above a 32-bit uniform (inversion of the Poisson distribution).
+// 32-bit half h (0..7) of a block: high then low half of words 0, 1, 2, 3.
+__device__ __forceinline__ uint32_t block_half(const uint64_t x[4], int h)
+{
+    const uint64_t w = h < 2 ? x[0] : h < 4 ? x[1] : h < 6 ? x[2] : x[3];
+    return (h & 1) ? static_cast<uint32_t>(w) : static_cast<uint32_t>(w >> 32);
+}
+
+// Number of CDF thresholds not above a 32-bit uniform (inversion of the
+// Poisson distribution).  The thresholds are non-decreasing, so this is the
+// first k with v < thr[k]; the first eight are compared without branches
+// (independent reads), the rest only when v passes the eighth.
+__device__ __forceinline__ int poisson_count(uint32_t v, const uint64_t *thr)
+{
+    const uint64_t x = v;
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) k += x >= thr[j] ? 1 : 0;
+    if (k == 8)
+        while (k < kPoisMaxDev && x >= thr[k]) ++k;
+    return k;
+}
+
+// Background spikes of neuron `local` at step n: one Philox block serves the
+// eight neurons 8*(local/8) .. +7, each taking its own 32-bit half.
 __device__ __forceinline__ int poisson_draw(uint64_t seed, int64_t n, int32_t local, const uint64_t *thr)
 {
-    const uint64_t v = philox_word0(static_cast<uint64_t>(n), static_cast<uint64_t>(local), 2, seed) >> 32;
-    int k = 0;
-    while (k < kPoisMaxDev && v >= thr[k]) ++k;
-    return k;
+    uint64_t x[4];
+    philox_block(static_cast<uint64_t>(n), static_cast<uint64_t>(local >> 3), 2, seed, x);
+    return poisson_count(block_half(x, local & 7), thr);
 }
 
 template <int WF>
@@ -279,22 +300,27 @@ hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st)
 // synapse rows stay in HBM; each spiking row is read once, every tile reading
 // only the sub-row that targets its own neurons.  Per step:
 //   1. update the tile (slot read/clear in LDS, Poisson, LIF), compact spikes;
-//   2. publish the tile's spikes as self-tagged 64-bit words (below);
-//   3. draw the next step's Poisson counts while the other tiles publish;
+//   2. publish the tile's spikes as self-tagged words (below);
+//   3. draw the next step's Philox blocks (waves that do not poll) while the
+//      other tiles publish;
 //   4. wait until every tile's word of this step (tiles of the same instance)
 //      is visible -- the step's only synchronisation -- and gather the ids;
 //   5. read this tile's sub-row of every spiking row and add the weights into
 //      the LDS ring with LDS integer atomics.
 //
-// Exchange protocol: each tile owns one word per step parity,
-//     bits 63..48 tag (step n + 1, 15 bits, top bit set), 47..32 spike count,
-//     31..0 first spike id,
-// and, for its 2nd, 3rd, ... spikes, entry words (tag32 = n + 1 | spike id).
+// Exchange protocol: each tile owns one 32-bit word per step parity,
+//     bits 31..30 tag ((n >> 1) & 1) + 1, 29..16 spike count,
+//     15..0 offset of the first spike in the tile,
+// and, for its 2nd, 3rd, ... spikes, 64-bit entry words (tag32 = n + 1 | id).
 // Words are written and polled with relaxed agent-scope atomics; a reader
 // accepts a word only when its tag matches, so no fence or counter is needed:
-// a 64-bit aligned store is seen whole or not at all.  A tile cannot publish
-// step n+2 (same parity) before it has seen every tile's step n+1 word, which
-// every tile writes only after finishing its reads of step n.
+// an aligned store is seen whole or not at all.  A tile cannot publish step
+// n+2 (same parity) before it has seen every tile's step n+1 word, which every
+// tile writes only after finishing its reads of step n, so the tag only has to
+// tell step n from step n-2 and from the zero the buffers start each launch
+// with.  The words of a step are polled by every tile of the instance; polling
+// starts after a short sleep, since polls issued while the last tiles'
+// stores are still in flight only congest the lines those stores go to.
 // ===========================================================================
 namespace mc {
 namespace {
@@ -416,20 +442,22 @@ __device__ void expand_segments(const int *s_pre, int nb, int c0, int cn, int *s
     lds_scan_max(s_seg, cn, s_wave);
 }
 
-__device__ __forceinline__ uint64_t load_word(const uint64_t *p)
+template <class W>
+__device__ __forceinline__ W load_word(const W *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void store_word(uint64_t *p, uint64_t v)
+template <class W>
+__device__ __forceinline__ void store_word(W *p, W v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Poll *p until `accept(word)`; false if the wait was abandoned (time-out or
 // another workgroup gave up).
-template <class Accept>
-__device__ __forceinline__ bool wait_word(const uint64_t *p, uint32_t *abort, StepCtl *ctl, Accept accept, uint64_t &w)
+template <class W, class Accept>
+__device__ __forceinline__ bool wait_word(const W *p, uint32_t *abort, StepCtl *ctl, Accept accept, W &w)
 {
     uint32_t spins = 0;
     for (;;) {
@@ -491,8 +519,12 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     int *ring = lds;                                   // [R][tmax] when LRING
     // global-ring variant: this workgroup's private, cache-line aligned slice
     int32_t *gring = LRING ? nullptr : P.gring + static_cast<size_t>(t) * R * P.gstride;
-    int *s_cnt = lds + (LRING ? R * tmax : 0);         // [T + 1] spike counts -> offsets
-    int *s_first = s_cnt + P.max_intiles + 1;          // [T] first spike id of each tile
+    // [2][tmax/8 + 2][4] Philox blocks of steps n + 1 and n + 2 (by step parity),
+    // one per group of 8 neurons (R * tmax is even: 8-byte aligned)
+    const int nbk = tmax / 8 + 2;
+    uint64_t *s_blk = reinterpret_cast<uint64_t *>(lds + (LRING ? R * tmax : 0));
+    int *s_cnt = reinterpret_cast<int *>(s_blk + 2 * 4 * nbk);   // [T + 1] spike counts -> offsets
+    int *s_first = s_cnt + P.max_intiles + 1;          // [T] first spike id of each tile (valid if it spiked)
     int *s_ids = s_first + P.max_intiles;              // [kSpkBatch]
     int *s_beg = s_ids + kSpkBatch;                    // [kSpkBatch] sub-row start
     int *s_pre = s_beg + kSpkBatch;                    // [kSpkBatch + 1] sub-row lengths -> offsets
@@ -510,52 +542,82 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     }
     if (l == 0) s_abort = 0;
 
+    // The tile lies in one instance: its seed and local numbering are uniform.
+    const uint64_t seed = B.seeds[B.meta[t0] >> 3];
+    const int32_t lo_local = t0 - td.inst_n0;
+    // Background input is pipelined over two steps: while step n waits for the
+    // other tiles, the highest threads draw the Philox blocks of step n + 2 (one
+    // per group of 8 neurons; at full scale in a wave that does not poll), and
+    // every thread turns the blocks of step n + 1, drawn a step earlier, into
+    // its neurons' counts.
+    const int g0 = lo_local >> 3, ng = ((lo_local + tlen - 1) >> 3) - g0 + 1;
+    auto fill_blocks = [&](int64_t m) {
+        uint64_t *dst = s_blk + static_cast<size_t>(m & 1) * 4 * nbk;
+        for (int j = nthr - 1 - l; j < ng; j += nthr) {
+            uint64_t x[4];
+            philox_block(static_cast<uint64_t>(m), static_cast<uint64_t>(g0 + j), 2, seed, x);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) dst[4 * j + w] = x[w];
+        }
+    };
+
     // neurons l, l + nthr, ... of the tile
     float u[NPT], I[NPT], cdc[NPT];
     int r[NPT], pop[NPT], kp[NPT];
-    int32_t local[NPT];
-    uint64_t seed[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int q = l + k * nthr;
         u[k] = I[k] = cdc[k] = 0.f;
         r[k] = pop[k] = kp[k] = 0;
-        local[k] = 0;
-        seed[k] = 0;
         if (q < tlen) {
             const int32_t i = t0 + q;
-            const uint32_t meta = B.meta[i];
-            const int inst = static_cast<int>(meta >> 3);
-            pop[k] = static_cast<int>(meta & 7u);
-            local[k] = i - B.inst_off[inst];
-            seed[k] = B.seeds[inst];
             u[k] = B.u[i];
             I[k] = B.cur[i];
             r[k] = B.refr[i];
+            pop[k] = static_cast<int>(B.meta[i] & 7u);
             cdc[k] = B.cdc[pop[k]];
         }
     }
     int64_t n = ctl->nbase;
     int64_t rec_base = ctl->rec_total;
     unsigned long long ev_acc = 0, pois_sum = 0;
-    __syncthreads();
+    auto counts = [&](int64_t m) {
+        const uint64_t *src = s_blk + static_cast<size_t>(m & 1) * 4 * nbk;
 #pragma unroll
-    for (int k = 0; k < NPT; ++k)
-        kp[k] = (l + k * nthr < tlen && B.poisson_on) ? poisson_draw(seed[k], n, local[k], s_thr + pop[k] * kPoisMaxDev) : 0;
+        for (int k = 0; k < NPT; ++k) {
+            const int loc = lo_local + l + k * nthr;
+            if (l + k * nthr < tlen) {
+                const uint64_t wd = src[4 * ((loc >> 3) - g0) + ((loc & 7) >> 1)];
+                kp[k] = poisson_count((loc & 1) ? static_cast<uint32_t>(wd) : static_cast<uint32_t>(wd >> 32),
+                                      s_thr + pop[k] * kPoisMaxDev);
+            }
+        }
+    };
+    __syncthreads();
+    if (B.poisson_on) {
+        fill_blocks(n);
+        fill_blocks(n + 1);
+    }
+    __syncthreads();
+    if (B.poisson_on) counts(n);
 
     // Optional per-step phase timestamps (100 MHz constant clock), thread 0 only:
-    // 0 step start, 1 spikes published, 2 (unused), 3 next Poisson drawn,
+    // 0 step start, 1 spikes published, 2 Philox block of step n + 2 and counts
+    // of step n + 1 done (by the last thread, which draws the tile's first
+    // block), 3 wait begins,
     // 4 every tile's word seen, 5 spike ids gathered, 6 delivery done,
     // 7 spike count of the step (this tile's instance).
     uint64_t *tr = nullptr;
     for (int64_t s = 0; s < steps; ++s, ++n) {
         const int par = static_cast<int>(n & 1);
-        const uint64_t tag16 = (static_cast<uint64_t>((n + 1) & 0x7FFF) | 0x8000u);
+        const uint32_t tag2 = static_cast<uint32_t>((n >> 1) & 1) + 1u;
         const uint64_t tag32 = static_cast<uint64_t>(static_cast<uint32_t>(n + 1));
-        uint64_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
+        uint32_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
         uint64_t *entries = P.xent + (static_cast<size_t>(par) * P.n_tiles + td.itile0) * tmax;
         const int slot = static_cast<int>(n & mask);
         tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
+        uint64_t *tr_blk = (P.trace && l == nthr - 1 && s < P.trace_steps)
+                               ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
         if (tr) tr[0] = __builtin_amdgcn_s_memrealtime();
         // ---- 1. neuron update ------------------------------------------------
         bool spike[NPT];
@@ -607,25 +669,30 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         }
         __syncthreads();
         if (l == 0) {
-            const uint64_t first = nspk ? static_cast<uint32_t>(s_own[0]) : 0u;
-            store_word(words + tl, (tag16 << 48) | (static_cast<uint64_t>(nspk) << 32) | first);
+            const uint32_t first = nspk ? static_cast<uint32_t>(s_own[0] - t0) : 0u;
+            store_word(words + tl, (tag2 << 30) | (static_cast<uint32_t>(nspk) << 16) | first);
         }
         if (tr) tr[1] = __builtin_amdgcn_s_memrealtime();
-        // ---- 3. next step's Poisson draw while the other tiles publish -----------
-#pragma unroll
-        for (int k = 0; k < NPT; ++k)
-            kp[k] = (l + k * nthr < tlen && B.poisson_on)
-                        ? poisson_draw(seed[k], n + 1, local[k], s_thr + pop[k] * kPoisMaxDev) : 0;
+        // ---- 3. background input: blocks of step n + 2 into the buffer whose
+        // blocks (step n) were all turned into counts before the last barrier;
+        // counts of step n + 1 from blocks drawn in the previous step -----------
         if (tr) tr[3] = __builtin_amdgcn_s_memrealtime();
+        if (B.poisson_on) {
+            fill_blocks(n + 2);
+            counts(n + 1);
+        }
+        if (tr_blk) tr_blk[2] = __builtin_amdgcn_s_memrealtime();
         // ---- 4. every tile's word of this step: counts and first ids --------------
+        if (l < T)
+            for (int z = 0; z < P.poll_delay; ++z) __builtin_amdgcn_s_sleep(1);
         for (int q = l; q < T; q += nthr) {
-            uint64_t w = 0;
-            if (!wait_word(words + q, P.abort, ctl, [tag16](uint64_t x) { return (x >> 48) == tag16; }, w)) {
+            uint32_t w = 0;
+            if (!wait_word(words + q, P.abort, ctl, [tag2](uint32_t x) { return (x >> 30) == tag2; }, w)) {
                 s_abort = 1;
                 break;
             }
-            s_cnt[q] = static_cast<int>((w >> 32) & 0xFFFFu);
-            s_first[q] = static_cast<int>(static_cast<uint32_t>(w));
+            s_cnt[q] = static_cast<int>((w >> 16) & 0x3FFFu);
+            s_first[q] = td.inst_n0 + q * td.stride + static_cast<int>(w & 0xFFFFu);
         }
         __syncthreads();
         if (s_abort) break;
@@ -830,8 +897,8 @@ TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring)
     sh.npt = tile_max <= 1024 ? 1 : tile_max <= 2048 ? 2 : 4;
     const int per_thread = (tile_max + sh.npt - 1) / sh.npt;
     sh.threads = ((per_thread + 63) / 64) * 64;
-    sh.lds = sizeof(int) * ((lds_ring ? static_cast<size_t>(ring) * tile_max : 0) + (2 * static_cast<size_t>(max_intiles) + 1) +
-                            3 * kSpkBatch + 1 + tile_max + kEvChunk);
+    sh.lds = sizeof(int) * ((lds_ring ? static_cast<size_t>(ring) * tile_max : 0) + 16 * (static_cast<size_t>(tile_max) / 8 + 2) +
+                            (2 * static_cast<size_t>(max_intiles) + 1) + 3 * kSpkBatch + 1 + tile_max + kEvChunk);
     return sh;
 }
 
@@ -890,7 +957,7 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     extern __shared__ int lds[];
     __shared__ int s_wave[17];
     const DevNet &B = P.base;
-    const int t = blockIdx.x + P.pad0;                // tiles of one instance: offset in pad0
+    const int t = blockIdx.x + P.tile_offset;         // tiles of one instance
     const TileDesc td = P.tiles[t];
     const int l = threadIdx.x, nthr = blockDim.x;
     const int mask = B.ring_mask, R = mask + 1;
@@ -963,7 +1030,7 @@ hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, i
                                int32_t count, int64_t n, hipStream_t st)
 {
     TiledNet arg = tn;
-    arg.pad0 = first_tile;
+    arg.tile_offset = first_tile;
     const size_t lds = inject_lds_bytes(tn.tile_max, tn.base.ring_mask + 1);
     const void *f = tn.syn_fmt == kSyn8F32 ? inject_tiled_fn<kSyn8F32>()
                   : tn.syn_fmt == kSyn8F16 ? inject_tiled_fn<kSyn8F16>()

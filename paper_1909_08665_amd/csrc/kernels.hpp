@@ -64,7 +64,7 @@ struct TileDesc {
     int32_t itile0;                   // first tile of this tile's instance
     int32_t intiles;                  // number of tiles of the instance
     int32_t inst_n0;                  // first neuron of the instance
-    int32_t pad;
+    int32_t stride;                   // nominal tile length of the instance: tile k starts at inst_n0 + k * stride
     int64_t sub_base;                 // index in `subrow` of this tile's row (one entry per neuron of its instance)
 };
 
@@ -81,14 +81,14 @@ struct TiledNet {
     int32_t n_tiles;
     int32_t tile_max;                 // largest tile (LDS / entry stride)
     int32_t max_intiles;              // most tiles of one instance
-    int32_t pad0;
+    int32_t tile_offset;              // injection: first tile of the launch
     const TileDesc *tiles;            // [n_tiles]
     const uint2 *subrow;              // per tile: [neurons of its instance] (first synapse, count) of the
                                       // sub-row of that presynaptic neuron that targets the tile
     const void *syn;                  // packed synapse records (SynFmt), CSR order
     int32_t syn_fmt;
-    int32_t pad2;
-    uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first id)
+    int32_t poll_delay;               // sleep before the first poll of a step, in units of 64 clocks
+    uint32_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first offset)
     uint64_t *xent;                   // [2][n_tiles][tile_max] further spike ids (tag32 | id)
     uint32_t *abort;                  // set when a wait gives up
     uint64_t *trace;                  // optional [trace_steps][n_tiles][8] phase timestamps

@@ -287,6 +287,30 @@ def test_checkpoint_resume_is_bit_exact(conn, tmp_path):
     assert e.value.code == -1
 
 
+def test_rewind_then_new_dynamics(conn, tmp_path):
+    """Loading a checkpoint moves the step index back; the spike-exchange words
+    written for the abandoned steps carry the tags the resumed run polls for and
+    must not be taken for its own (here the resumed run differs: u is halved)."""
+    _say("rewind")
+    path = str(tmp_path / "rw.ckpt")
+    net = mc.Network.build(44, 0.2, conn)
+    orc = _oracle(44, 0.2, conn)
+    net.run(300)
+    orc.run(300)
+    assert _same_run(net, orc) > 0
+    net.save(path)
+    net.run(600)                      # the abandoned future
+    net.spikes()
+    net.load(path)
+    u, I, r = orc.state()
+    u2 = (u.astype(np.float32) * np.float32(0.5)).astype(np.float64)
+    net.set_state(u=u2.astype(np.float32))
+    orc.set_state(u=u2)
+    net.run(600)
+    orc.run(600)
+    assert _same_run(net, orc) > 0
+
+
 def test_autotuner_keeps_results(conn):
     _say("autotune")
     net = mc.Network.build(43, 0.05, conn)

@@ -114,6 +114,19 @@ def test_poisson_counts_distribution():
         assert stats.chi2.sf(chi2, kmax) > 1e-4
 
 
+def test_poisson_counts_independent_within_a_block():
+    """Eight neurons share one Philox block per step (one 32-bit half each):
+    their counts must be uncorrelated and individually Poisson."""
+    net = O.OracleNet.build_explicit([16, 0, 0, 0, 0, 0, 0, 0], [], [], [], [])
+    lam = 8.0 * O.K_EXT[0] * 1e-4
+    steps = 20000
+    k = np.array([[net.poisson_count(n, i) for i in range(16)] for n in range(steps)], dtype=np.float64)
+    assert np.all(np.abs(k.mean(axis=0) - lam) < 5 * math.sqrt(lam / steps))
+    c = np.corrcoef(k.T)
+    off = c[~np.eye(16, dtype=bool)]
+    assert np.max(np.abs(off)) < 5 / math.sqrt(steps)
+
+
 # ---------------------------------------------------------------------------
 # Single-neuron closed forms
 # ---------------------------------------------------------------------------
