@@ -17,6 +17,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -544,22 +545,81 @@ int absorb(mc_net *nt, const mc::StepCtl &c, const int32_t *rec_ids, const int32
     const int64_t total = c.rec_total;
     const int64_t got = std::min(total, nt->rec_cap);
     const auto &rp = nt->host.row_ptr;
+    const auto &meta = nt->host.meta;
+    const int n_inst = nt->host.n_inst;
     span = std::max<int64_t>(1, span);
-    std::vector<int32_t> per_step(static_cast<size_t>(span), 0);
-    std::vector<int32_t> per_inst_step;
-    if (nt->host.n_inst > 1) per_inst_step.assign(static_cast<size_t>(span) * nt->host.n_inst, 0);
-    for (int64_t q = 0; q < got; ++q) {
-        const int32_t gid = rec_ids[q];
-        const int inst = static_cast<int>(nt->host.meta[gid] >> 3);
-        const int64_t st = rec_steps[q];
-        nt->unread[inst].emplace_back(st, gid - nt->host.inst_off[inst]);
-        nt->inst_spikes[inst] += 1;
-        nt->inst_events[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
-        const int64_t k = st - s0;
-        if (k >= 0 && k < span) {
-            per_step[k] += 1;
-            if (!per_inst_step.empty()) per_inst_step[static_cast<size_t>(k) * nt->host.n_inst + inst] += 1;
+    // Threads take contiguous chunks of the record: a first pass counts spikes,
+    // events and per-step spikes per instance, a second writes each spike into
+    // its instance's list at the offset the counts give (order within a list
+    // does not matter: mc_get_spikes sorts).
+    const int nth = got < (int64_t{1} << 12) ? 1
+                                           : static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    struct Part {
+        std::vector<int64_t> cnt, ev;
+        std::vector<int32_t> per_step, per_inst_step;
+    };
+    std::vector<Part> part(static_cast<size_t>(nth));
+    auto chunk = [got, nth](int t, int64_t &q0, int64_t &q1) {
+        q0 = got * t / nth;
+        q1 = got * (t + 1) / nth;
+    };
+    auto count = [&](int t) {
+        Part &P = part[static_cast<size_t>(t)];
+        P.cnt.assign(n_inst, 0);
+        P.ev.assign(n_inst, 0);
+        P.per_step.assign(static_cast<size_t>(span), 0);
+        if (n_inst > 1) P.per_inst_step.assign(static_cast<size_t>(span) * n_inst, 0);
+        int64_t q0, q1;
+        chunk(t, q0, q1);
+        for (int64_t q = q0; q < q1; ++q) {
+            const int32_t gid = rec_ids[q];
+            const int inst = static_cast<int>(meta[gid] >> 3);
+            P.cnt[inst] += 1;
+            P.ev[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
+            const int64_t k = rec_steps[q] - s0;
+            if (k >= 0 && k < span) {
+                P.per_step[k] += 1;
+                if (n_inst > 1) P.per_inst_step[static_cast<size_t>(k) * n_inst + inst] += 1;
+            }
         }
+    };
+    std::vector<std::vector<int64_t>> at(static_cast<size_t>(nth), std::vector<int64_t>(n_inst));
+    auto place = [&](int t) {
+        std::vector<int64_t> &cur = at[static_cast<size_t>(t)];
+        int64_t q0, q1;
+        chunk(t, q0, q1);
+        for (int64_t q = q0; q < q1; ++q) {
+            const int32_t gid = rec_ids[q];
+            const int inst = static_cast<int>(meta[gid] >> 3);
+            nt->unread[inst][static_cast<size_t>(cur[inst]++)] = {rec_steps[q], gid - nt->host.inst_off[inst]};
+        }
+    };
+    auto parallel = [nth](auto &&f) {
+        if (nth == 1) {
+            f(0);
+            return;
+        }
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; ++t) pool.emplace_back(f, t);
+        f(0);
+        for (auto &th : pool) th.join();
+    };
+    parallel(count);
+    for (int j = 0; j < n_inst; ++j) {
+        int64_t off = static_cast<int64_t>(nt->unread[j].size());
+        for (int t = 0; t < nth; ++t) {
+            at[static_cast<size_t>(t)][j] = off;
+            off += part[static_cast<size_t>(t)].cnt[j];
+            nt->inst_spikes[j] += part[static_cast<size_t>(t)].cnt[j];
+            nt->inst_events[j] += part[static_cast<size_t>(t)].ev[j];
+        }
+        nt->unread[j].resize(static_cast<size_t>(off));
+    }
+    parallel(place);
+    std::vector<int32_t> &per_step = part[0].per_step, &per_inst_step = part[0].per_inst_step;
+    for (int t = 1; t < nth; ++t) {
+        for (int64_t k = 0; k < span; ++k) per_step[k] += part[static_cast<size_t>(t)].per_step[k];
+        for (size_t k = 0; k < per_inst_step.size(); ++k) per_inst_step[k] += part[static_cast<size_t>(t)].per_inst_step[k];
     }
     for (int64_t k = 0; k < span; ++k) {
         nt->max_step_spikes = std::max<int64_t>(nt->max_step_spikes, per_step[k]);

@@ -188,6 +188,24 @@ def test_batch_instances_equal_single_runs(conn):
         assert tot["max_spikes_per_step"] >= max(net.counters(j)["max_spikes_per_step"] for j in range(4))
 
 
+def test_batch_segments_with_many_spikes(conn):
+    """Several 10-15 % instances over 3000 steps: recorder segments of 10^5+
+    spikes, drained on the host while the next segment runs, in parallel
+    chunks; every instance still equals its single run."""
+    seeds, scales = [211, 212, 213, 214, 215, 216], [0.1, 0.12, 0.15, 0.1, 0.11, 0.13]
+    _say("batch many spikes", seeds, scales)
+    net = mc.Network.build_batch(seeds, scales, conn)
+    net.run(3000)
+    total = 0
+    for j, (s, sc) in enumerate(zip(seeds, scales)):
+        orc = _oracle(s, sc, conn)
+        orc.run(3000)
+        total += _same_run(net, orc, inst=j)
+        assert net.counters(j)["events"] == orc.counters()["events"]
+        assert net.counters(j)["max_spikes_per_step"] == orc.counters()["max_spikes_per_step"]
+    assert total > 100000
+
+
 def test_dc_input_hook_parity(conn):
     _say("dc input")
     i_dc = [420.0, 380.0, 500.0, 0.0, 650.0, 390.0, 0.0, 800.0]

@@ -3,18 +3,20 @@ oracle's FP64 mode (same network, seed 1, full scale, 10 s, first 1 s
 discarded): per-population firing rate, CV of the inter-spike interval and
 binned-count correlation (Sec. 4b of Rhodes et al., arXiv 1909.08665).
 
-Chaotic dynamics make FP32 and FP64 runs diverge spike by spike, so the
-comparison is statistical.  The FP64 reference values and their run-to-run
-spread on the same network (independent Poisson streams) come from
-tests/golden/fp64_stats_full.json, written by tests/golden/make_fp64_stats.py
-from the oracle alone.  Tolerance per population: rates within
-max(2 %, 2 x FP64 relative range), CV-ISI within max(5 %, 2 x FP64 range) for
-the FP32 store.  The FP16/BF16 stores perturb every weight by up to 2^-11 / 2^-8
-relative; on the stand-in network that perturbation acts like a different
-network realisation and can move a population's operating point well beyond
-the FP64 run-to-run spread (FP64 runs on other seeds differ by up to 40 %), so
-for them the per-population errors are reported and only the whole-network
-rate is bounded (within 30 %).
+Chaotic dynamics make FP32 and FP64 runs diverge spike by spike once a
+rounding difference flips one threshold decision, so the comparison is
+statistical.  tests/golden/fp64_stats_full.json (written by
+tests/golden/make_fp64_stats.py from the oracle alone) holds the FP64 run with
+the model's background stream and four FP64 runs that differ from it only by
+one neuron forced to spike in the first step -- the smallest discrete change
+of a run.  Their largest deviation from the reference is the noise floor of a
+run with the same background input; the FP32 store must stay within
+max(2 %, 2 x floor) of the FP64 rate and max(5 %, 2 x floor) of its CV-ISI.
+The FP16/BF16 stores perturb every weight by up to 2^-11 / 2^-8 relative; on
+the stand-in network that acts like a different network realisation and can
+move a population's operating point well beyond that floor, so for them the
+per-population errors are reported and only the whole-network rate is bounded
+(within 30 %).
 """
 import json
 import os
@@ -34,14 +36,15 @@ STEPS, DISCARD = 100000, 10000
 
 def _fp64_reference():
     data = json.load(open(GOLDEN))
-    runs = [data[k]["stats"] for k in ("1", "1/stream1", "1/stream2") if k in data]
-    assert len(runs) >= 2, "golden FP64 statistics missing"
+    base = data["1"]["stats"]
+    pert = [data[k]["stats"] for k in ("1/perturb1", "1/perturb2", "1/perturb3", "1/perturb4") if k in data]
+    assert len(pert) >= 2, "golden FP64 statistics missing"
     ref = {}
     for p in POP_NAMES:
-        r = np.array([x[p]["rate_hz"] for x in runs])
-        c = np.array([x[p]["cv_isi"] for x in runs])
-        ref[p] = dict(rate=r[0], rate_tol=max(0.02, 2 * (r.max() - r.min()) / r.mean()),
-                      cv=c[0], cv_tol=max(0.05, 2 * (c.max() - c.min()) / c.mean()))
+        r0, c0 = base[p]["rate_hz"], base[p]["cv_isi"]
+        fr = max(abs(x[p]["rate_hz"] - r0) / r0 for x in pert)
+        fc = max(abs(x[p]["cv_isi"] - c0) / c0 for x in pert)
+        ref[p] = dict(rate=r0, rate_tol=max(0.02, 2 * fr), cv=c0, cv_tol=max(0.05, 2 * fc))
     return ref
 
 
