@@ -55,8 +55,8 @@ def cpu_baseline(seed, scale, conn, warm, steps):
                       f"({steps * DT_S:.2f} s biological time), build excluded"}
 
 
-PHASES = (("update+publish", 0, 1), ("next Poisson", 1, 3), ("wait for all tiles", 3, 4),
-          ("spike ids + sub-row pointers", 4, 5), ("delivery", 5, 6))
+PHASES = (("update+publish", 0, 1), ("wait for all tiles", 3, 4),
+          ("spike ids + sub-row entries", 4, 5), ("delivery", 5, 6))
 
 
 def step_latency(net):
@@ -137,6 +137,88 @@ def delivery_microbench(net, info, args, conn_desc):
             "rows": rows}
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_tiled_full_scale_fp32.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1909_08665_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic_per_step():
+    """HBM bytes per step of k_tiled on the full-scale FP32 workload from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE record, each counter scaled by
+    what it reads for a copy of known size; None when the record is missing or
+    was taken on a different kernel source than the one built here."""
+    import hashlib
+    try:
+        line = next(l for l in open(PROFILE) if l.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    f = dict(x.strip().rsplit(" ", 1) for x in line.split(":", 1)[1].split(";"))
+    if f.get("kernels.hip sha256") != hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest():
+        return None
+    total = float(f["fetch KiB"]) * float(f["fetch factor"]) + float(f["write KiB"]) * float(f["write factor"])
+    return total * 1024 / float(f["steps per launch"])
+
+
+def stability_run(args, mc, conn):
+    """Long full-scale run (hours of biological time) in 10 s windows: the
+    per-population rate of every window, the fitted drift of each population's
+    rate (per cent of its mean per hour, first window discarded), error flags,
+    a checkpoint every 10 biological minutes, and at the end a bit-exact check
+    that a fresh network resumed from the last checkpoint continues the run."""
+    import tempfile
+
+    from synth_inputs import FULL_SIZE, POP_NAMES
+    win = 100000                                   # 10 s
+    windows = max(2, int(round(args.stability * 3600 / 10)))
+    net = mc.Network.build(args.seed, 1.0, conn, wfmt=WFMT[args.wfmt])
+    sizes = np.array(FULL_SIZE, dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    rates = np.zeros((windows, 8))
+    ckpt = os.path.join(tempfile.gettempdir(), f"mc_stability_{os.getpid()}.ckpt")
+    ckpt_ms = []
+    t0 = time.perf_counter()
+    for w in range(windows):
+        net.run(win)
+        _, ids = net.spikes()
+        pop = np.searchsorted(off, ids, side="right") - 1
+        rates[w] = np.bincount(pop, minlength=8)[:8] / (sizes * win * DT_S)
+        if (w + 1) % 60 == 0:
+            tc = time.perf_counter()
+            net.save(ckpt)
+            ckpt_ms.append((time.perf_counter() - tc) * 1e3)
+        if (w + 1) % 6 == 0:
+            log(f"stability: {(w + 1) * 10 / 60:.0f} biological min, wall {time.perf_counter() - t0:.1f}s, "
+                f"rates {np.round(rates[w], 3).tolist()}")
+    wall = time.perf_counter() - t0
+    c = net.counters()
+    hours = (np.arange(1, windows) + 0.5) * 10 / 3600
+    drift = {}
+    for a, name in enumerate(POP_NAMES):
+        r = rates[1:, a]
+        slope = np.polyfit(hours, r, 1)[0] if len(r) > 1 else 0.0
+        drift[name] = {"mean_hz": round(float(r.mean()), 4), "sd_hz": round(float(r.std()), 4),
+                       "slope_pct_per_h": round(float(100 * slope / r.mean()), 3) if r.mean() > 0 else None}
+    # resume check: continue 2000 steps, then replay them from the last checkpoint
+    net.save(ckpt)
+    net.run(2000)
+    sa = net.spikes()
+    fresh = mc.Network.build(args.seed, 1.0, conn, wfmt=WFMT[args.wfmt])
+    fresh.load(ckpt)
+    fresh.run(2000)
+    sb = fresh.spikes()
+    resumed = bool(np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1]))
+    os.remove(ckpt)
+    fresh.close()
+    net.close()
+    return {"metric": "stability (full scale, long run)", "unit": "x real time", "value": round(windows * win * DT_S / wall, 4),
+            "data": "synthetic", "dtype": "f32",
+            "config": {"workload": f"microcircuit scale 1.0, {args.wfmt.upper()} store, "
+                                   f"{windows * 10 / 3600:g} h biological time in 10 s windows", "seed": args.seed},
+            "steps": windows * win, "wall_s": round(wall, 2), "spikes": c["spikes"], "events": c["events"],
+            "max_spikes_per_step": c["max_spikes_per_step"], "error_flags": "none: every mc_run returned MC_OK (a recorder overflow or a timed-out wait raises)",
+            "drift": drift, "checkpoint_ms": [round(x, 1) for x in ckpt_ms], "resume_bit_exact": resumed,
+            "window_rates_hz": np.round(rates, 4).tolist()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +242,8 @@ def main():
                     help="delivery microbenchmark: inject forced spike lists of 25..77169 neurons")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device twice (reference for HBM byte counters) and exit")
+    ap.add_argument("--stability", type=float, default=0, metavar="HOURS",
+                    help="long full-scale run of HOURS biological time: per-window rates, drift, checkpoints")
     ap.add_argument("--trace", type=int, default=0,
                     help="record per-step phase timestamps for the first K timed steps (tiled engine)")
     args = ap.parse_args()
@@ -188,6 +272,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4, "copies": 2}), flush=True)
         return
     conn = standin_conn_table()
+    if args.stability:
+        print(json.dumps(stability_run(args, mc, conn)), flush=True)
+        return
     engine = {"auto": mc.ENGINE_AUTO, "graph": mc.ENGINE_GRAPH, "tiled": mc.ENGINE_TILED}[args.engine]
 
     seeds, scales = workload(args)
@@ -257,8 +344,13 @@ def main():
     algo_bytes = events * b_event + spikes * per_spike + args.steps * n_neurons * per_neuron_step
     avg_launch_ms = kernel_ms / max(1, launches)
     achieved = algo_bytes / max(1, launches) / (avg_launch_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
+    traffic = None
+    if tiled and n_inst == 1 and args.config == "full" and args.wfmt == "fp32" and scales[0] == 1.0 and launches:
+        per_step = measured_traffic_per_step()
+        if per_step is not None:
+            traffic = int(per_step * args.steps / launches)
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None, "kernel": kname,
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": kname,
                 "launches": launches, "avg_launch_ms": round(avg_launch_ms, 4),
                 "bytes_per_launch": int(algo_bytes / max(1, launches))}
 

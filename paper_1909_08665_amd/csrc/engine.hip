@@ -359,11 +359,11 @@ void plan_tiles(const mc_net *nt, int target, std::vector<mc::TileDesc> &tiles, 
             d.intiles = T;
             d.inst_n0 = n0;
             d.stride = len;
-            d.sub_base = sub_total;              // this tile's row: one entry per neuron of the instance
+            d.sub_base = sub_total + k;          // entry of (presynaptic p, tile k): sub_base + p * T
             tiles.push_back(d);
             tile_max = std::max(tile_max, d.len);
-            sub_total += nn;
         }
+        sub_total += static_cast<int64_t>(nn) * T;
         max_intiles = std::max<int>(max_intiles, T);
     }
 }
@@ -433,7 +433,7 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
         if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
     const mc::DevNet d = dev_view(nt);
-    HIP_TRY(mc::launch_subrows(d, nt->tiles_dev, T, sub_total, nt->subrow, nt->stream));
+    HIP_TRY(mc::launch_subrows(d, nt->tiles_dev, T, nt->host.n, nt->subrow, nt->stream));
     {
         std::vector<int32_t> tile_of(static_cast<size_t>(nt->host.n));
         for (int k = 0; k < T; ++k)

@@ -497,6 +497,20 @@ __device__ __forceinline__ int syn_record(const void *__restrict__ syn, uint32_t
     return __float2int_rn(f * 256.0f);
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b mod 8),
+// each XCD with its own L2.  Workgroup b takes tile rank(b) in the order
+// (b mod 8, b / 8), so that every XCD holds a contiguous run of tiles: the
+// cache lines that neighbouring tiles' sub-rows and sub-row entries share are
+// then fetched into one L2.  A bijection of [0, n); speed only.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int x = b % kXcds;
+    int base = 0;
+    for (int y = 0; y < x; ++y) base += (n - y + kXcds - 1) / kXcds;
+    return base + b / kXcds;
+}
+
 template <int SF, bool LRING, int NPT>
 __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
 {
@@ -508,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
 
     const DevNet &B = P.base;
     StepCtl *ctl = B.ctl;
-    const int t = blockIdx.x, tmax = P.tile_max;
+    const int t = xcd_tile(blockIdx.x, gridDim.x), tmax = P.tile_max;
     const TileDesc td = P.tiles[t];
     const int tl = t - td.itile0, T = td.intiles;     // local tile index, tiles of the instance
     const int l = threadIdx.x, nthr = blockDim.x;
@@ -747,7 +761,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                     }
                     pre = static_cast<int>(static_cast<uint32_t>(w));
                 }
-                const uint2 sr = P.subrow[td.sub_base + (pre - td.inst_n0)];
+                const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T];
                 s_beg[q] = static_cast<int>(sr.x);
                 s_pre[q] = static_cast<int>(sr.y);
             }
@@ -815,30 +829,35 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
 // Sub-row table: entry (tile t, presynaptic neuron i of t's instance) = first
 // synapse and count of the part of row i whose targets lie in tile t (rows are
 // sorted by target, so that part is contiguous).
+// One thread per presynaptic neuron i: cut its row (sorted by target) at the
+// boundaries of its instance's tiles and write the (first, count) pairs of all
+// those tiles side by side, entry sub_base(tile) + (i - inst_n0) * T.
 __global__ void k_subrows(const uint64_t *row_ptr, const int32_t *tgt, const TileDesc *tiles, int n_tiles,
-                          int64_t entries, uint2 *subrow)
+                          int64_t n_neurons, uint2 *subrow)
 {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= entries) return;
-    int lo = 0, hi = n_tiles;                      // tile whose row holds entry q
+    if (q >= n_neurons) return;
+    const int32_t i = static_cast<int32_t>(q);
+    int lo = 0, hi = n_tiles;                      // tile holding neuron i: its instance's tiles
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (tiles[mid].sub_base <= q) lo = mid; else hi = mid;
+        if (tiles[mid].t0 <= i) lo = mid; else hi = mid;
     }
-    const TileDesc td = tiles[lo];
-    const int32_t i = td.inst_n0 + static_cast<int32_t>(q - td.sub_base);
-    const int32_t k0 = td.t0, k1 = td.t0 + td.len;
-    uint64_t a = row_ptr[i], b = row_ptr[i + 1];
-    while (a < b) {
-        const uint64_t mid = (a + b) >> 1;
-        if (tgt[mid] < k0) a = mid + 1; else b = mid;
+    const int first = tiles[lo].itile0, T = tiles[lo].intiles;
+    const int64_t p = i - tiles[lo].inst_n0;
+    uint64_t a = row_ptr[i];
+    const uint64_t end = row_ptr[i + 1];
+    for (int k = 0; k < T; ++k) {
+        const TileDesc td = tiles[first + k];
+        const int32_t k1 = td.t0 + td.len;
+        uint64_t c = a, e = end;                   // first synapse at or beyond the tile's end
+        while (c < e) {
+            const uint64_t mid = (c + e) >> 1;
+            if (tgt[mid] < k1) c = mid + 1; else e = mid;
+        }
+        subrow[td.sub_base + p * T] = make_uint2(static_cast<uint32_t>(a), static_cast<uint32_t>(c - a));
+        a = c;
     }
-    uint64_t c = a, e = row_ptr[i + 1];
-    while (c < e) {
-        const uint64_t mid = (c + e) >> 1;
-        if (tgt[mid] < k1) c = mid + 1; else e = mid;
-    }
-    subrow[q] = make_uint2(static_cast<uint32_t>(a), static_cast<uint32_t>(c - a));
 }
 
 // Packed record of every synapse (grid-stride over the store).
@@ -910,13 +929,13 @@ hipError_t tiled_max_coresident(int syn_fmt, const TiledShape &sh, int *blocks_p
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, sh.threads, sh.lds);
 }
 
-hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t entries, uint2 *subrow,
+hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t n_neurons, uint2 *subrow,
                           hipStream_t st)
 {
-    const int64_t blocks = (entries + 255) / 256;
+    const int64_t blocks = (n_neurons + 255) / 256;
     if (blocks < 1) return hipSuccess;
     hipLaunchKernelGGL(k_subrows, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d.row_ptr, d.tgt, tiles_dev,
-                       n_tiles, entries, subrow);
+                       n_tiles, n_neurons, subrow);
     return hipGetLastError();
 }
 
@@ -971,7 +990,7 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     for (int b0 = 0; b0 < count; b0 += kSpkBatch) {
         const int nb = min(kSpkBatch, count - b0);
         for (int q = l; q < nb; q += nthr) {
-            const uint2 sr = P.subrow[td.sub_base + (ids[b0 + q] - td.inst_n0)];
+            const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(ids[b0 + q] - td.inst_n0) * td.intiles];
             s_beg[q] = static_cast<int>(sr.x);
             s_pre[q] = static_cast<int>(sr.y);
         }

@@ -65,7 +65,7 @@ struct TileDesc {
     int32_t intiles;                  // number of tiles of the instance
     int32_t inst_n0;                  // first neuron of the instance
     int32_t stride;                   // nominal tile length of the instance: tile k starts at inst_n0 + k * stride
-    int64_t sub_base;                 // index in `subrow` of this tile's row (one entry per neuron of its instance)
+    int64_t sub_base;                 // `subrow` entry of (presynaptic p, this tile) is sub_base + p * intiles
 };
 
 // Packed synapse records of the tiled engine, in CSR order (so a sub-row is a
@@ -83,7 +83,7 @@ struct TiledNet {
     int32_t max_intiles;              // most tiles of one instance
     int32_t tile_offset;              // injection: first tile of the launch
     const TileDesc *tiles;            // [n_tiles]
-    const uint2 *subrow;              // per tile: [neurons of its instance] (first synapse, count) of the
+    const uint2 *subrow;              // per instance: [its neurons][its tiles] (first synapse, count) of the
                                       // sub-row of that presynaptic neuron that targets the tile
     const void *syn;                  // packed synapse records (SynFmt), CSR order
     int32_t syn_fmt;
@@ -126,7 +126,7 @@ hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, i
 hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int64_t n, hipStream_t st);
 // Device-side construction of the tiled engine's sub-row table and packed
 // synapse store (rows sorted by target; tile_of: tile index of every neuron).
-hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t entries, uint2 *subrow,
+hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t n_neurons, uint2 *subrow,
                           hipStream_t st);
 hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, const int32_t *tile_of, int64_t m,
                                 int syn_fmt, void *syn, hipStream_t st);
