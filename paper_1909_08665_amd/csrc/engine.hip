@@ -1399,7 +1399,7 @@ int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t 
         tn.syn_fmt = net->syn_fmt;
         int first = 0;
         while (net->tiles_host[first].inst_n0 != off) ++first;
-        const int threads = std::min(1024, ((net->tile_max + 63) / 64) * 64);
+        const int threads = 1024;   // events, not neurons, spread over the threads: more loads in flight
         HIP_TRY(mc::launch_inject_tiled(tn, first, net->tiles_host[first].intiles, threads, net->inject_buf,
                                         static_cast<int32_t>(count), net->step, net->stream));
     } else {

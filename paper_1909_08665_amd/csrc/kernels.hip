@@ -326,6 +326,9 @@ namespace mc {
 namespace {
 
 constexpr int kSpkBatch = 2048;              // spikes processed per delivery batch
+constexpr int kDeliverU = 4;                 // records in flight per thread in the step kernel's delivery
+constexpr int kInjectU = 8;                  // and in the injection kernel
+constexpr int kInjBatch = 2048;              // spikes per batch of the injection kernel
 constexpr uint32_t kSpinLimit = 1u << 24;    // polls before a wait gives up
 
 // Exclusive prefix sum of one value per thread, in thread order; returns the
@@ -387,61 +390,6 @@ __device__ __forceinline__ int find_segment(const int *a, int n, int key)
     return lo;
 }
 
-// Inclusive running maximum of a[0..count) in LDS (values >= -1).
-__device__ void lds_scan_max(int *a, int count, int *s_wave)
-{
-    const int per = (count + blockDim.x - 1) / blockDim.x;
-    const int beg = min(count, static_cast<int>(threadIdx.x) * per);
-    const int end = min(count, beg + per);
-    int m = -1;
-    for (int q = beg; q < end; ++q) m = max(m, a[q]);
-    // exclusive max over the threads before this one
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
-    int incl = m;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int x = __shfl_up(incl, o, 64);
-        if (lane >= o) incl = max(incl, x);
-    }
-    if (lane == 63) s_wave[wave] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = -1;
-        for (int q = 0; q < nwaves; ++q) {
-            const int x = s_wave[q];
-            s_wave[q] = run;
-            run = max(run, x);
-        }
-    }
-    __syncthreads();
-    int run = max(s_wave[wave], __shfl_up(incl, 1, 64));
-    if (lane == 0) run = s_wave[wave];
-    for (int q = beg; q < end; ++q) {
-        run = max(run, a[q]);
-        a[q] = run;
-    }
-    __syncthreads();
-}
-
-constexpr int kEvChunk = 2048;               // events expanded per pass
-
-// For events c0 .. c0+cn-1 of a batch whose segment offsets are s_pre[0..nb]
-// (exclusive prefix, s_pre[nb] = total), write the owning segment of each event
-// into s_seg[0..cn): scatter segment starts, then a running maximum.
-__device__ void expand_segments(const int *s_pre, int nb, int c0, int cn, int *s_seg, int *s_wave)
-{
-    for (int x = threadIdx.x; x < cn; x += blockDim.x) s_seg[x] = -1;
-    __syncthreads();
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-        const int p = s_pre[q];
-        if (s_pre[q + 1] > p && p >= c0 && p < c0 + cn) s_seg[p - c0] = q;   // non-empty segments start apart
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && s_seg[0] < 0) s_seg[0] = find_segment(s_pre, nb + 1, c0);
-    __syncthreads();
-    lds_scan_max(s_seg, cn, s_wave);
-}
-
 template <class W>
 __device__ __forceinline__ W load_word(const W *p)
 {
@@ -497,6 +445,37 @@ __device__ __forceinline__ int syn_record(const void *__restrict__ syn, uint32_t
     return __float2int_rn(f * 256.0f);
 }
 
+// Add the events of nb spikes into a ring: spike q's sub-row is records
+// s_beg[q] .. s_beg[q] + len - 1, s_pre the exclusive prefix of the lengths
+// (s_pre[nb] = E), so event e belongs to the last q with s_pre[q] <= e.
+// Thread l takes events l, l + nthr, ... in rounds of U (consecutive lanes read
+// consecutive records): it finds their spikes (independent binary searches in
+// LDS), loads all U records, then adds them -- U loads in flight per thread
+// and no barrier, whatever the mix of sub-row lengths.  add(target, delay, wq)
+// does the ring update.
+template <int SF, int U, class Add>
+__device__ __forceinline__ void deliver_events(const void *__restrict__ syn, const int *s_beg, const int *s_pre, int nb,
+                                               int E, Add add)
+{
+    const int l = threadIdx.x, nthr = blockDim.x;
+    for (int e0 = 0; e0 < E; e0 += U * nthr) {
+        uint32_t j[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int e = e0 + l + k * nthr;
+            const int q = e < E ? find_segment(s_pre, nb + 1, e) : 0;
+            j[k] = e < E ? static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(e - s_pre[q]) : 0u;
+        }
+        int wq[U], tg[U], d[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (e0 + l + k * nthr < E) wq[k] = syn_record<SF>(syn, j[k], tg[k], d[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (e0 + l + k * nthr < E) add(tg[k], d[k], wq[k]);
+    }
+}
+
 // Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b mod 8),
 // each XCD with its own L2.  Workgroup b takes tile rank(b) in the order
 // (b mod 8, b / 8), so that every XCD holds a contiguous run of tiles: the
@@ -543,7 +522,6 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     int *s_beg = s_ids + kSpkBatch;                    // [kSpkBatch] sub-row start
     int *s_pre = s_beg + kSpkBatch;                    // [kSpkBatch + 1] sub-row lengths -> offsets
     int *s_own = s_pre + kSpkBatch + 1;                // [tmax] this tile's spikes
-    int *s_seg = s_own + tmax;                         // [kEvChunk] owning spike of each event
 
     for (int q = l; q < 8 * kPoisMaxDev; q += nthr) s_thr[q] = B.pois_thr[q];
     for (int s = 0; s < R; ++s) {
@@ -771,27 +749,14 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             lds_scan_excl(s_pre, nb, s_wave);
             const int E = s_pre[nb];
             ev_acc += static_cast<unsigned long long>(E);
-            auto deliver = [&](int e, int q) {
-                const uint32_t j = static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(e - s_pre[q]);
-                int tg, d;
-                const int wq = syn_record<SF>(P.syn, j, tg, d);
+            deliver_events<SF, kDeliverU>(P.syn, s_beg, s_pre, nb, E, [&](int tg, int d, int wq) {
                 const int ds = static_cast<int>((n + d) & mask);
                 if (LRING)
                     atomicAdd(ring + ds * tmax + tg, wq);
                 else
                     __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-            };
-            if (nb <= 32) {
-                for (int e = l; e < E; e += nthr) deliver(e, find_segment(s_pre, nb + 1, e));
-            } else {
-                for (int c0 = 0; c0 < E; c0 += kEvChunk) {
-                    const int cn = min(kEvChunk, E - c0);
-                    expand_segments(s_pre, nb, c0, cn, s_seg, s_wave);
-                    for (int x = l; x < cn; x += nthr) deliver(c0 + x, s_seg[x]);
-                    __syncthreads();
-                }
-            }
+            });
             __syncthreads();
         }
         if (s_abort) break;
@@ -917,7 +882,7 @@ TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring)
     const int per_thread = (tile_max + sh.npt - 1) / sh.npt;
     sh.threads = ((per_thread + 63) / 64) * 64;
     sh.lds = sizeof(int) * ((lds_ring ? static_cast<size_t>(ring) * tile_max : 0) + 16 * (static_cast<size_t>(tile_max) / 8 + 2) +
-                            (2 * static_cast<size_t>(max_intiles) + 1) + 3 * kSpkBatch + 1 + tile_max + kEvChunk);
+                            (2 * static_cast<size_t>(max_intiles) + 1) + 3 * kSpkBatch + 1 + tile_max);
     return sh;
 }
 
@@ -982,13 +947,12 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     const int mask = B.ring_mask, R = mask + 1;
     const int tmax = P.tile_max, tlen = td.len;
     int *ring = lds;                                  // [R][tmax]
-    int *s_beg = ring + R * tmax;                     // [kSpkBatch]
-    int *s_pre = s_beg + kSpkBatch;                   // [kSpkBatch + 1]
-    int *s_seg = s_pre + kSpkBatch + 1;               // [kEvChunk]
+    int *s_beg = ring + R * tmax;                     // [kInjBatch]
+    int *s_pre = s_beg + kInjBatch;                   // [kInjBatch + 1]
     for (int q = l; q < R * tmax; q += nthr) ring[q] = 0;
     __syncthreads();
-    for (int b0 = 0; b0 < count; b0 += kSpkBatch) {
-        const int nb = min(kSpkBatch, count - b0);
+    for (int b0 = 0; b0 < count; b0 += kInjBatch) {
+        const int nb = min(kInjBatch, count - b0);
         for (int q = l; q < nb; q += nthr) {
             const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(ids[b0 + q] - td.inst_n0) * td.intiles];
             s_beg[q] = static_cast<int>(sr.x);
@@ -997,18 +961,9 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
         __syncthreads();
         lds_scan_excl(s_pre, nb, s_wave);
         const int E = s_pre[nb];
-        for (int c0 = 0; c0 < E; c0 += kEvChunk) {
-            const int cn = min(kEvChunk, E - c0);
-            expand_segments(s_pre, nb, c0, cn, s_seg, s_wave);
-            for (int x = l; x < cn; x += nthr) {
-                const int q = s_seg[x];
-                const uint32_t j = static_cast<uint32_t>(s_beg[q]) + static_cast<uint32_t>(c0 + x - s_pre[q]);
-                int tg, d;
-                const int wq = syn_record<SF>(P.syn, j, tg, d);
-                atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, wq);
-            }
-            __syncthreads();
-        }
+        deliver_events<SF, kInjectU>(P.syn, s_beg, s_pre, nb, E, [&](int tg, int d, int wq) {
+            atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, wq);
+        });
         __syncthreads();
     }
     for (int s = 0; s < R; ++s)
@@ -1042,7 +997,7 @@ const void *inject_tiled_fn() { return reinterpret_cast<const void *>(&k_inject_
 
 size_t inject_lds_bytes(int tile_max, int ring)
 {
-    return sizeof(int) * (static_cast<size_t>(ring) * tile_max + 2 * kSpkBatch + 1 + kEvChunk);
+    return sizeof(int) * (static_cast<size_t>(ring) * tile_max + 2 * kInjBatch + 1);
 }
 
 hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
