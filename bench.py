@@ -233,6 +233,8 @@ def main():
     ap.add_argument("--engine", choices=["auto", "graph", "tiled"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--step-budget", type=float, default=0, metavar="US",
+                    help="lossy real-time mode: drop deliveries past US microseconds into a step (tiled engine)")
     ap.add_argument("--poll-delay", type=int, default=0,
                     help="tiled engine: sleep before polling, units of 64 clocks (-1 none, 0 library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -288,6 +290,8 @@ def main():
         net.set_launch(engine=mc.ENGINE_TILED, tile=args.tile)
     if args.poll_delay:
         net.set_launch(poll_delay=args.poll_delay)
+    if args.step_budget:
+        net.set_step_budget(args.step_budget)
     info = net.info()
     n_neurons, n_syn = info["n_neurons"], info["n_synapses"]
     log(f"build+upload {time.time() - t:.1f}s: {n_inst} instance(s), {n_neurons} neurons, {n_syn} synapses")
@@ -378,6 +382,9 @@ def main():
                    "n_tiles": info["n_tiles"], "ring_depth": info["ring_depth"],
                    "poll_delay": info["poll_delay"] if tiled else None},
         "events_per_s": round(events / wall, 1),
+        **({"step_budget_us": args.step_budget,
+            "dropped_events_frac": round((c1["dropped_events"] - c0["dropped_events"]) / max(1, events), 6)}
+           if args.step_budget else {}),
         "spikes_per_step": round(spikes / args.steps, 3),
         "max_spikes_per_step": c1["max_spikes_per_step"],
         "context": {"paper_spinnaker_rtf": 1.0, "paper_spinnaker_events_per_s": 9.343e8},

@@ -106,6 +106,8 @@ typedef struct mc_counters {
     int64_t poisson_events;      /* background spikes drawn (whole network, all instances) */
     int64_t max_spikes_per_step; /* largest spike count in one step (of `instance`, or of the
                                     whole network for instance = -1) */
+    int64_t dropped_events;      /* events not delivered because a step ran past its budget
+                                    (mc_set_step_budget); 0 when no budget is set */
 } mc_counters;
 
 typedef struct mc_info {
@@ -240,6 +242,19 @@ int mc_set_launch(struct mc_net *net, const mc_launch *l);
 int mc_tune(struct mc_net *net, int64_t trial_steps);
 
 /* Use the caller's HIP stream (hipStream_t passed as void*); NULL = own stream. */
+/*
+ * Lossy real-time mode (Sec. 3a(iii) and 4a: a core that has not finished a
+ * step's synaptic processing when the next timer tick comes drops what is left
+ * and counts it).  With budget_us > 0 every tile of the TILED engine stops
+ * delivering a step's spikes once budget_us has passed since it started that
+ * step; the events it did not deliver are dropped and counted in
+ * mc_counters.dropped_events.  Results then depend on timing and no longer
+ * match a run without a budget.  budget_us = 0 (the default) turns it off.
+ * Errors: MC_ERR_ARG (negative or above 20,000,000 us); mc_run returns
+ * MC_ERR_UNSUPPORTED on the GRAPH engine while a budget is set.
+ */
+int mc_set_step_budget(struct mc_net *net, double budget_us);
+
 int mc_set_stream(struct mc_net *net, void *hip_stream);
 
 /*

@@ -42,7 +42,7 @@ class McConfig(C.Structure):
 
 class McCounters(C.Structure):
     _fields_ = [("steps", C.c_int64), ("spikes", C.c_int64), ("events", C.c_int64),
-                ("poisson_events", C.c_int64), ("max_spikes_per_step", C.c_int64)]
+                ("poisson_events", C.c_int64), ("max_spikes_per_step", C.c_int64), ("dropped_events", C.c_int64)]
 
 
 class McInfo(C.Structure):
@@ -63,7 +63,7 @@ EXPORTS = ("mc_config_default", "mc_build_network", "mc_build_batch", "mc_run", 
            "mc_get_state", "mc_set_state", "mc_get_counters", "mc_get_info", "mc_get_csr",
            "mc_instance_size", "mc_set_launch", "mc_tune", "mc_set_stream", "mc_set_timing",
            "mc_get_timing", "mc_set_trace", "mc_get_trace", "mc_save_state", "mc_load_state", "mc_free",
-           "mc_last_error", "mc_inject_spikes")
+           "mc_last_error", "mc_inject_spikes", "mc_set_step_budget")
 
 _lib = None
 
@@ -108,6 +108,7 @@ def lib():
     L.mc_get_trace.argtypes = [P, P, I64, C.POINTER(I64)]
     L.mc_save_state.argtypes = [P, C.c_char_p]
     L.mc_load_state.argtypes = [P, C.c_char_p]
+    L.mc_set_step_budget.argtypes = [P, C.c_double]
     L.mc_free.argtypes = [P]
     L.mc_free.restype = None
     _lib = L
@@ -195,6 +196,12 @@ class Network:
         0 keeps the current value of any knob."""
         l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid, poll_delay)
         _check(lib().mc_set_launch(self._h, C.byref(l)))
+
+    def set_step_budget(self, budget_us):
+        """Lossy real-time mode (tiled engine): per step, events not delivered
+        within budget_us of the step's start are dropped and counted in
+        counters()["dropped_events"]; 0 turns it off."""
+        _check(lib().mc_set_step_budget(self._h, float(budget_us)))
 
     def tune(self, trial_steps=200):
         _check(lib().mc_tune(self._h, int(trial_steps)))

@@ -104,6 +104,9 @@ struct mc_net {
     int32_t syn_fmt = 0;
     uint32_t *xchg = nullptr;
     uint64_t *xent = nullptr;
+    unsigned long long *dropped_acc = nullptr;   // [2][n_tiles], one half per recorder
+    unsigned long long *h_dropped = nullptr;     // pinned copy
+    uint32_t budget_ticks = 0;                   // step budget, 100 MHz ticks; 0: none
     int64_t xent_high = 0;            // entry words may carry tags of steps below this
     uint32_t *abort_flag = nullptr;
     uint64_t *trace = nullptr;
@@ -128,6 +131,7 @@ struct mc_net {
     int64_t step = 0;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;   // per instance
     std::vector<int64_t> inst_spikes, inst_events, inst_max_step;
+    std::vector<int64_t> inst_dropped;  // events dropped by the step budget, per instance
     int64_t max_step_spikes = 0;
     int64_t steps_in_flight = 0;      // steps of the segment being drained
     bool overflow = false;
@@ -194,12 +198,12 @@ void release(mc_net *nt)
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
                     nt->rec_id, nt->rec_step, nt->subrow, nt->syn, nt->xchg, nt->xent, nt->abort_flag, nt->trace,
-                    nt->tiles_dev, nt->gring, nt->inject_buf, nt->rec_id1, nt->rec_step1};
+                    nt->tiles_dev, nt->gring, nt->inject_buf, nt->rec_id1, nt->rec_step1, nt->dropped_acc};
     for (void *b : bufs)
         if (b) hipFree(b);
     for (void *b : {static_cast<void *>(nt->h_rec_id), static_cast<void *>(nt->h_rec_step), static_cast<void *>(nt->h_ctl),
                     static_cast<void *>(nt->h_rec_id1), static_cast<void *>(nt->h_rec_step1),
-                    static_cast<void *>(nt->h_ctl1)})
+                    static_cast<void *>(nt->h_ctl1), static_cast<void *>(nt->h_dropped)})
         if (b) hipHostFree(b);
     if (nt->ev0) hipEventDestroy(nt->ev0);
     if (nt->ev1) hipEventDestroy(nt->ev1);
@@ -404,8 +408,11 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     if (nt->tile == target && nt->tiled_shape.lds_ring == sh.lds_ring && nt->subrow) return MC_OK;
     for (void *b : {static_cast<void *>(nt->subrow), static_cast<void *>(nt->syn), static_cast<void *>(nt->xchg),
                     static_cast<void *>(nt->xent), static_cast<void *>(nt->abort_flag), static_cast<void *>(nt->tiles_dev),
-                    static_cast<void *>(nt->gring)})
+                    static_cast<void *>(nt->gring), static_cast<void *>(nt->dropped_acc)})
         if (b) hipFree(b);
+    if (nt->h_dropped) hipHostFree(nt->h_dropped);
+    nt->dropped_acc = nullptr;
+    nt->h_dropped = nullptr;
     nt->gring = nullptr;
     nt->gstride = 0;
     nt->subrow = nullptr;
@@ -418,8 +425,10 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     int rc;
     if ((rc = dalloc(&nt->subrow, static_cast<size_t>(sub_total))) || (rc = dalloc(&nt->xchg, 2 * T)) ||
         (rc = dalloc(&nt->xent, static_cast<size_t>(2) * T * tile_max)) || (rc = dalloc(&nt->abort_flag, 1)) ||
-        (rc = dalloc(&nt->tiles_dev, T)))
+        (rc = dalloc(&nt->tiles_dev, T)) || (rc = dalloc(&nt->dropped_acc, 2 * static_cast<size_t>(T))))
         return rc;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_dropped), 2 * static_cast<size_t>(T) * sizeof(unsigned long long),
+                          hipHostMallocDefault));
     if (!sh.lds_ring) {
         nt->gstride = ((tile_max + 31) / 32) * 32;
         if ((rc = dalloc(&nt->gring, static_cast<size_t>(T) * nt->host.ring * nt->gstride))) return rc;
@@ -519,6 +528,7 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
     nt->unread.assign(n, {});
     nt->inst_spikes.assign(n, 0);
     nt->inst_events.assign(n, 0);
+    nt->inst_dropped.assign(n, 0);
     nt->inst_max_step.assign(n, 0);
     nt->engine = MC_ENGINE_GRAPH;
     if (cfg->engine != MC_ENGINE_GRAPH) {
@@ -710,6 +720,10 @@ int run_tiled(mc_net *nt, int64_t steps)
             nt->kernel_ms += ms;
             nt->launches += 1;
         }
+        for (int k = 0; k < nt->n_tiles; ++k) {
+            const unsigned long long dr = nt->h_dropped[static_cast<size_t>(p.buf) * nt->n_tiles + k];
+            if (dr) nt->inst_dropped[nt->host.meta[nt->tiles_host[k].t0] >> 3] += static_cast<int64_t>(dr);
+        }
         const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
         const int rc = absorb(nt, c, h_ids, h_steps, p.s0, p.len);
         const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
@@ -727,6 +741,9 @@ int run_tiled(mc_net *nt, int64_t steps)
         nt->xent_high = std::max(nt->xent_high, nt->step + seg);
         tn.base.rec_id = buf ? nt->rec_id1 : nt->rec_id;
         tn.base.rec_step = buf ? nt->rec_step1 : nt->rec_step;
+        tn.dropped = nt->dropped_acc + static_cast<size_t>(buf) * nt->n_tiles;
+        tn.budget_ticks = nt->budget_ticks;
+        HIP_TRY(hipMemsetAsync(tn.dropped, 0, nt->n_tiles * sizeof(unsigned long long), nt->stream));
         // Tile words from an earlier launch carry older tags; clearing them rules out
         // a tag match across a jump of the step index (engine switch).
         HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint32_t), nt->stream));
@@ -738,6 +755,8 @@ int run_tiled(mc_net *nt, int64_t steps)
         if (timing) HIP_TRY(hipEventRecord(nt->seg_ev1[buf], nt->stream));
         HIP_TRY(hipMemcpyAsync(buf ? nt->h_ctl1 : nt->h_ctl, nt->ctl, sizeof(mc::StepCtl), hipMemcpyDeviceToHost,
                                nt->stream));
+        HIP_TRY(hipMemcpyAsync(nt->h_dropped + static_cast<size_t>(buf) * nt->n_tiles, tn.dropped,
+                               nt->n_tiles * sizeof(unsigned long long), hipMemcpyDeviceToHost, nt->stream));
         HIP_TRY(hipEventRecord(nt->snap_ev[buf], nt->stream));
         if (pend.buf >= 0) rc = finish(pend);
         pend = {nt->step, seg, buf};
@@ -784,6 +803,7 @@ int ensure_graph(mc_net *nt)
 
 int run_graph(mc_net *nt, int64_t steps)
 {
+    if (nt->budget_ticks) return fail(MC_ERR_UNSUPPORTED, "the step budget needs the tiled engine");
     int rc = ensure_graph(nt);
     if (rc) return rc;
     const mc::DevNet d = dev_view(nt);
@@ -833,7 +853,7 @@ struct Snapshot {
     std::vector<unsigned long long> pois;
     int64_t step = 0;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;
-    std::vector<int64_t> inst_spikes, inst_events, inst_max_step;
+    std::vector<int64_t> inst_spikes, inst_events, inst_max_step, inst_dropped;
     int64_t max_step_spikes = 0;
 };
 
@@ -856,6 +876,7 @@ int take_snapshot(mc_net *nt, Snapshot &s)
     s.unread = nt->unread;
     s.inst_spikes = nt->inst_spikes;
     s.inst_events = nt->inst_events;
+    s.inst_dropped = nt->inst_dropped;
     s.inst_max_step = nt->inst_max_step;
     s.max_step_spikes = nt->max_step_spikes;
     return MC_OK;
@@ -875,12 +896,13 @@ int restore_snapshot(mc_net *nt, const Snapshot &s)
     nt->unread = s.unread;
     nt->inst_spikes = s.inst_spikes;
     nt->inst_events = s.inst_events;
+    nt->inst_dropped = s.inst_dropped;
     nt->inst_max_step = s.inst_max_step;
     nt->max_step_spikes = s.max_step_spikes;
     return MC_OK;
 }
 
-constexpr char kCkptMagic[8] = {'M', 'C', 'C', 'K', 'P', 'T', '0', '2'};
+constexpr char kCkptMagic[8] = {'M', 'C', 'C', 'K', 'P', 'T', '0', '3'};
 
 template <class T>
 bool put(std::FILE *f, const T *p, size_t n) { return std::fwrite(p, sizeof(T), n, f) == n; }
@@ -902,6 +924,7 @@ int write_checkpoint(mc_net *nt, const char *path)
               put(f, s.refr.data(), s.refr.size()) && put(f, s.ring.data(), s.ring.size()) && put(f, &s.ctl, 1) &&
               put(f, s.pois.data(), s.pois.size()) && put(f, s.inst_spikes.data(), s.inst_spikes.size()) &&
               put(f, s.inst_events.data(), s.inst_events.size()) && put(f, s.inst_max_step.data(), s.inst_max_step.size()) &&
+              put(f, s.inst_dropped.data(), s.inst_dropped.size()) &&
               put(f, &s.max_step_spikes, 1);
     for (const auto &v : s.unread) {
         const int64_t k = static_cast<int64_t>(v.size());
@@ -938,11 +961,13 @@ int read_checkpoint(mc_net *nt, const char *path)
     s.inst_spikes.resize(nt->host.n_inst);
     s.inst_events.resize(nt->host.n_inst);
     s.inst_max_step.resize(nt->host.n_inst);
+    s.inst_dropped.resize(nt->host.n_inst);
     s.unread.resize(nt->host.n_inst);
     ok = get(f, &s.step, 1) && get(f, s.u.data(), N) && get(f, s.cur.data(), N) && get(f, s.refr.data(), N) &&
          get(f, s.ring.data(), s.ring.size()) && get(f, &s.ctl, 1) && get(f, s.pois.data(), s.pois.size()) &&
          get(f, s.inst_spikes.data(), s.inst_spikes.size()) && get(f, s.inst_events.data(), s.inst_events.size()) &&
-         get(f, s.inst_max_step.data(), s.inst_max_step.size()) && get(f, &s.max_step_spikes, 1);
+         get(f, s.inst_max_step.data(), s.inst_max_step.size()) && get(f, s.inst_dropped.data(), s.inst_dropped.size()) &&
+         get(f, &s.max_step_spikes, 1);
     for (auto &v : s.unread) {
         int64_t k = 0;
         ok = ok && get(f, &k, 1) && k >= 0 && k < (int64_t{1} << 40);
@@ -1011,11 +1036,12 @@ int autotune(mc_net *nt, int64_t trial_steps)
             const int64_t tile = fitting_tile(nt, cap, std::max<int64_t>(64, (N + cap - 1) / cap));
             if (tile <= 4096) cands.push_back({MC_ENGINE_TILED, static_cast<int>(tile), ring, 0, 0, 0, 0, -1});
         }
-    for (int block : {128, 256, 512})
-        for (int seg : {128, 256, 512})
-            for (int grid : {512, 2048})
-                for (int chunk : {32, 128})
-                    cands.push_back({MC_ENGINE_GRAPH, 0, 0, chunk, seg, block, grid, 0});
+    if (!nt->budget_ticks)            // the step budget needs the tiled engine
+        for (int block : {128, 256, 512})
+            for (int seg : {128, 256, 512})
+                for (int grid : {512, 2048})
+                    for (int chunk : {32, 128})
+                        cands.push_back({MC_ENGINE_GRAPH, 0, 0, chunk, seg, block, grid, 0});
     double best = 1e300;
     Candidate pick{nt->engine, nt->tile, nt->tiled_shape.lds_ring ? 1 : 2, nt->graph_chunk, nt->seg, nt->block,
                    nt->deliver_grid, nt->poll_delay_set ? nt->poll_delay : -1};
@@ -1199,10 +1225,12 @@ int mc_get_counters(mc_net *net, int32_t instance, mc_counters *out)
     out->steps = net->step;
     out->spikes = 0;
     out->events = 0;
+    out->dropped_events = 0;
     for (int j = 0; j < net->host.n_inst; ++j)
         if (instance < 0 || instance == j) {
             out->spikes += net->inst_spikes[j];
             out->events += net->inst_events[j];
+            out->dropped_events += net->inst_dropped[j];
         }
     int64_t pe = 0;
     for (auto v : acc) pe += static_cast<int64_t>(v);
@@ -1312,6 +1340,15 @@ int mc_set_launch(mc_net *net, const mc_launch *l)
         if (rc) return rc;
         net->engine = MC_ENGINE_TILED;
     }
+    return MC_OK;
+}
+
+int mc_set_step_budget(mc_net *net, double budget_us)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (!(budget_us >= 0.0) || budget_us > 2.0e7) return fail(MC_ERR_ARG, "budget_us must be in [0, 2e7]");
+    const double ticks = std::nearbyint(budget_us * 100.0);        // s_memrealtime runs at 100 MHz
+    net->budget_ticks = budget_us > 0.0 ? static_cast<uint32_t>(std::max(1.0, ticks)) : 0u;
     return MC_OK;
 }
 

@@ -452,13 +452,20 @@ __device__ __forceinline__ int syn_record(const void *__restrict__ syn, uint32_t
 // consecutive records): it finds their spikes (independent binary searches in
 // LDS), loads all U records, then adds them -- U loads in flight per thread
 // and no barrier, whatever the mix of sub-row lengths.  add(target, delay, wq)
-// does the ring update.
+// does the ring update.  With a budget (100 MHz ticks since t_step, 0 for
+// none), a wave that finds the budget spent before a round stops and adds the
+// number of its threads' remaining events to `dropped`.
 template <int SF, int U, class Add>
 __device__ __forceinline__ void deliver_events(const void *__restrict__ syn, const int *s_beg, const int *s_pre, int nb,
-                                               int E, Add add)
+                                               int E, Add add, uint64_t t_step = 0, uint32_t budget = 0,
+                                               unsigned long long *dropped = nullptr)
 {
     const int l = threadIdx.x, nthr = blockDim.x;
     for (int e0 = 0; e0 < E; e0 += U * nthr) {
+        if (budget && __builtin_amdgcn_s_memrealtime() - t_step > budget) {
+            if (e0 + l < E) *dropped += static_cast<unsigned long long>((E - (e0 + l) + nthr - 1) / nthr);
+            return;
+        }
         uint32_t j[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -572,7 +579,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     }
     int64_t n = ctl->nbase;
     int64_t rec_base = ctl->rec_total;
-    unsigned long long ev_acc = 0, pois_sum = 0;
+    unsigned long long ev_acc = 0, pois_sum = 0, drop_acc = 0;
     auto counts = [&](int64_t m) {
         const uint64_t *src = s_blk + static_cast<size_t>(m & 1) * 4 * nbk;
 #pragma unroll
@@ -607,6 +614,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         uint32_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
         uint64_t *entries = P.xent + (static_cast<size_t>(par) * P.n_tiles + td.itile0) * tmax;
         const int slot = static_cast<int>(n & mask);
+        const uint64_t t_step = P.budget_ticks ? __builtin_amdgcn_s_memrealtime() : 0;
         tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
         uint64_t *tr_blk = (P.trace && l == nthr - 1 && s < P.trace_steps)
                                ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
@@ -749,14 +757,17 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             lds_scan_excl(s_pre, nb, s_wave);
             const int E = s_pre[nb];
             ev_acc += static_cast<unsigned long long>(E);
-            deliver_events<SF, kDeliverU>(P.syn, s_beg, s_pre, nb, E, [&](int tg, int d, int wq) {
-                const int ds = static_cast<int>((n + d) & mask);
-                if (LRING)
-                    atomicAdd(ring + ds * tmax + tg, wq);
-                else
-                    __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            });
+            deliver_events<SF, kDeliverU>(
+                P.syn, s_beg, s_pre, nb, E,
+                [&](int tg, int d, int wq) {
+                    const int ds = static_cast<int>((n + d) & mask);
+                    if (LRING)
+                        atomicAdd(ring + ds * tmax + tg, wq);
+                    else
+                        __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                },
+                t_step, P.budget_ticks, &drop_acc);
             __syncthreads();
         }
         if (s_abort) break;
@@ -778,10 +789,14 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     for (int s2 = 0; s2 < R; ++s2)
         for (int q = l; q < tlen; q += nthr)
             B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = LRING ? ring[s2 * tmax + q] : gring[s2 * P.gstride + q];
-    unsigned long long ps = pois_sum;
+    unsigned long long ps = pois_sum, dr = drop_acc;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+        ps += __shfl_xor(ps, o, 64);
+        dr += __shfl_xor(dr, o, 64);
+    }
     if ((l & 63) == 0 && ps) atomicAdd(&B.pois_acc[t], ps);
+    if ((l & 63) == 0 && dr) atomicAdd(&P.dropped[t], dr);
     if (l == 0 && !s_abort) {
         atomicAdd(&ctl->events, ev_acc);
         if (t == 0) {

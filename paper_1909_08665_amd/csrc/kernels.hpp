@@ -94,6 +94,9 @@ struct TiledNet {
     uint64_t *trace;                  // optional [trace_steps][n_tiles][8] phase timestamps
     int32_t trace_steps;
     int32_t gstride;                  // global-ring variant: ints per slot row (multiple of 32)
+    unsigned long long *dropped;      // [n_tiles] events dropped by the step budget (this launch)
+    uint32_t budget_ticks;            // step budget in 100 MHz clock ticks; 0: none
+    int32_t pad3;
     int32_t *gring;                   // global-ring variant: [n_tiles][R][gstride], one slice per workgroup
 };
 

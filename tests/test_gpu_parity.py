@@ -329,6 +329,43 @@ def test_rewind_then_new_dynamics(conn, tmp_path):
     assert _same_run(net, orc) > 0
 
 
+def test_step_budget_off_or_ample_changes_nothing(conn):
+    """Lossy real-time mode: a budget no step comes near delivers everything,
+    exactly as without one."""
+    _say("step budget ample")
+    net = mc.Network.build(45, 0.05, conn)
+    orc = _oracle(45, 0.05, conn)
+    net.set_step_budget(1e6)
+    net.run(1500)
+    orc.run(1500)
+    assert _same_run(net, orc) > 0
+    assert net.counters()["dropped_events"] == 0
+
+
+def test_step_budget_spent_drops_every_event(conn):
+    """With a budget of one clock tick every tile finds it spent before its first
+    delivery round, so every recurrent event is dropped and counted: the run
+    equals the oracle's run of the same neurons without synapses, and the
+    dropped count equals the events of the recorded spikes."""
+    _say("step budget spent")
+    net = mc.Network.build(46, 0.05, conn)
+    orc = _oracle(46, 0.05, np.zeros(64))
+    net.set_step_budget(0.01)
+    net.run(1500)
+    orc.run(1500)
+    assert _same_run(net, orc) > 0
+    c = net.counters()
+    assert c["events"] > 0 and c["dropped_events"] == c["events"]
+    net.set_step_budget(0)
+    with pytest.raises(mc.MCError):
+        net.set_step_budget(-1)
+    g = mc.Network.build(46, 0.05, conn, engine=mc.ENGINE_GRAPH)
+    g.set_step_budget(5.0)
+    with pytest.raises(mc.MCError) as e:
+        g.run(10)
+    assert e.value.code == -9          # MC_ERR_UNSUPPORTED
+
+
 def test_autotuner_keeps_results(conn):
     _say("autotune")
     net = mc.Network.build(43, 0.05, conn)
