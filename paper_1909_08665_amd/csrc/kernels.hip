@@ -497,7 +497,9 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return base + b / kXcds;
 }
 
-template <int SF, bool LRING, int NPT>
+// BUDGET: the lossy real-time form (P.budget_ticks > 0); a separate
+// instantiation, so that the step kernel without a budget carries none of it.
+template <int SF, bool LRING, int NPT, bool BUDGET>
 __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
 {
     extern __shared__ int lds[];
@@ -614,7 +616,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         uint32_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
         uint64_t *entries = P.xent + (static_cast<size_t>(par) * P.n_tiles + td.itile0) * tmax;
         const int slot = static_cast<int>(n & mask);
-        const uint64_t t_step = P.budget_ticks ? __builtin_amdgcn_s_memrealtime() : 0;
+        const uint64_t t_step = BUDGET ? __builtin_amdgcn_s_memrealtime() : 0;
         tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
         uint64_t *tr_blk = (P.trace && l == nthr - 1 && s < P.trace_steps)
                                ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
@@ -767,7 +769,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                         __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
                 },
-                t_step, P.budget_ticks, &drop_acc);
+                t_step, BUDGET ? P.budget_ticks : 0u, &drop_acc);
             __syncthreads();
         }
         if (s_abort) break;
@@ -796,7 +798,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         dr += __shfl_xor(dr, o, 64);
     }
     if ((l & 63) == 0 && ps) atomicAdd(&B.pois_acc[t], ps);
-    if ((l & 63) == 0 && dr) atomicAdd(&P.dropped[t], dr);
+    if (BUDGET && (l & 63) == 0 && dr) atomicAdd(&P.dropped[t], dr);
     if (l == 0 && !s_abort) {
         atomicAdd(&ctl->events, ev_acc);
         if (t == 0) {
@@ -859,31 +861,32 @@ __global__ void k_pack_synapses(const int32_t *tgt, const uint8_t *dly, const vo
 }
 
 template <int SF, bool LR, int NPT>
-const void *tiled_fn3()
+const void *tiled_fn3(bool budget)
 {
-    return reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT>);
+    return budget ? reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, true>)
+                  : reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, false>);
 }
 
 template <int SF, bool LR>
-const void *tiled_fn2(int npt)
+const void *tiled_fn2(int npt, bool budget)
 {
-    return npt == 1 ? tiled_fn3<SF, LR, 1>() : npt == 2 ? tiled_fn3<SF, LR, 2>() : tiled_fn3<SF, LR, 4>();
+    return npt == 1 ? tiled_fn3<SF, LR, 1>(budget) : npt == 2 ? tiled_fn3<SF, LR, 2>(budget) : tiled_fn3<SF, LR, 4>(budget);
 }
 
 template <int SF>
-const void *tiled_fn1(bool lr, int npt)
+const void *tiled_fn1(bool lr, int npt, bool budget)
 {
-    return lr ? tiled_fn2<SF, true>(npt) : tiled_fn2<SF, false>(npt);
+    return lr ? tiled_fn2<SF, true>(npt, budget) : tiled_fn2<SF, false>(npt, budget);
 }
 
-const void *tiled_kernel(int sf, bool lr, int npt)
+const void *tiled_kernel(int sf, bool lr, int npt, bool budget)
 {
     switch (sf) {
-    case kSyn8F32: return tiled_fn1<kSyn8F32>(lr, npt);
-    case kSyn8F16: return tiled_fn1<kSyn8F16>(lr, npt);
-    case kSyn8BF16: return tiled_fn1<kSyn8BF16>(lr, npt);
-    case kSyn4F16: return tiled_fn1<kSyn4F16>(lr, npt);
-    default: return tiled_fn1<kSyn4BF16>(lr, npt);
+    case kSyn8F32: return tiled_fn1<kSyn8F32>(lr, npt, budget);
+    case kSyn8F16: return tiled_fn1<kSyn8F16>(lr, npt, budget);
+    case kSyn8BF16: return tiled_fn1<kSyn8BF16>(lr, npt, budget);
+    case kSyn4F16: return tiled_fn1<kSyn4F16>(lr, npt, budget);
+    default: return tiled_fn1<kSyn4BF16>(lr, npt, budget);
     }
 }
 
@@ -903,10 +906,18 @@ TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring)
 
 hipError_t tiled_max_coresident(int syn_fmt, const TiledShape &sh, int *blocks_per_cu)
 {
-    const void *f = tiled_kernel(syn_fmt, sh.lds_ring, sh.npt);
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, sh.threads, sh.lds);
+    // both forms (with and without a step budget) must fit
+    *blocks_per_cu = 1 << 30;
+    for (bool budget : {false, true}) {
+        const void *f = tiled_kernel(syn_fmt, sh.lds_ring, sh.npt, budget);
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
+        if (e != hipSuccess) return e;
+        int b = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, sh.threads, sh.lds);
+        if (e != hipSuccess) return e;
+        *blocks_per_cu = std::min(*blocks_per_cu, b);
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t n_neurons, uint2 *subrow,
@@ -933,7 +944,7 @@ hipError_t launch_tiled(const TiledNet &tn, const TiledShape &sh, int64_t steps,
     TiledNet arg = tn;
     int64_t nsteps = steps;
     void *args[] = {&arg, &nsteps};
-    return hipLaunchCooperativeKernel(tiled_kernel(tn.syn_fmt, sh.lds_ring, sh.npt), dim3(tn.n_tiles),
+    return hipLaunchCooperativeKernel(tiled_kernel(tn.syn_fmt, sh.lds_ring, sh.npt, tn.budget_ticks != 0), dim3(tn.n_tiles),
                                       dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
 }
 
