@@ -233,6 +233,7 @@ def main():
     ap.add_argument("--engine", choices=["auto", "graph", "tiled"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--device-build", action="store_true", help="draw and sort the synapse store on the GPU")
     ap.add_argument("--step-budget", type=float, default=0, metavar="US",
                     help="lossy real-time mode: drop deliveries past US microseconds into a step (tiled engine)")
     ap.add_argument("--poll-delay", type=int, default=0,
@@ -282,10 +283,11 @@ def main():
     seeds, scales = workload(args)
     n_inst = len(seeds)
     t = time.time()
+    db = int(args.device_build)
     if n_inst == 1:
-        net = mc.Network.build(seeds[0], scales[0], conn, wfmt=WFMT[args.wfmt], engine=engine)
+        net = mc.Network.build(seeds[0], scales[0], conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db)
     else:
-        net = mc.Network.build_batch(seeds, scales, conn, wfmt=WFMT[args.wfmt], engine=engine)
+        net = mc.Network.build_batch(seeds, scales, conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db)
     if args.tile:
         net.set_launch(engine=mc.ENGINE_TILED, tile=args.tile)
     if args.poll_delay:

@@ -97,6 +97,12 @@ typedef struct mc_config {
     double w_ext_pa;             /* background weight: 87.8 */
     double d_mean_exc_ms, d_sd_exc_ms;   /* 1.5, 0.75 */
     double d_mean_inh_ms, d_sd_inh_ms;   /* 0.8, 0.4 */
+    int32_t device_build;        /* 0: draw and sort the synapses on the host (default);
+                                    1: on the GPU -- the same draws and row order, with the
+                                    device's log/sqrt/cos/sin (a quantised weight or delay
+                                    can differ from the host build's only when its exact
+                                    value lies within ~1e-13 of a rounding boundary).
+                                    Needs fewer than 2^24 neurons and 2^32 synapses. */
 } mc_config;
 
 typedef struct mc_counters {

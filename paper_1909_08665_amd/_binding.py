@@ -37,6 +37,7 @@ class McConfig(C.Structure):
         ("l4e_l23e_factor", C.c_double), ("w_ext_pa", C.c_double),
         ("d_mean_exc_ms", C.c_double), ("d_sd_exc_ms", C.c_double),
         ("d_mean_inh_ms", C.c_double), ("d_sd_inh_ms", C.c_double),
+        ("device_build", C.c_int32),
     ]
 
 

@@ -37,7 +37,7 @@ def build(verbose=False):
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("kernels.hip", "engine.hip"):
+    for src in ("kernels.hip", "engine.hip", "devbuild.hip"):
         obj = os.path.join(BUILD, src + ".o")
         _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/mc.h"
+#include "devbuild.hpp"
 #include "kernels.hpp"
 #include "model.hpp"
 
@@ -219,6 +220,7 @@ int params_from_config(const mc_config *cfg, mc::ModelParams &p)
 {
     if (!cfg) return fail(MC_ERR_ARG, "cfg must not be NULL (the connection table has no default)");
     if (cfg->struct_size != sizeof(mc_config)) return fail(MC_ERR_ARG, "cfg->struct_size mismatch (use mc_config_default)");
+    if (cfg->device_build != 0 && cfg->device_build != 1) return fail(MC_ERR_ARG, "device_build must be 0 or 1");
     if (!cfg->conn_probs) return fail(MC_ERR_ARG, "cfg->conn_probs is required");
     if (cfg->wfmt < MC_W_FP32 || cfg->wfmt > MC_W_BF16) return fail(MC_ERR_ARG, "unknown weight format");
     if (cfg->engine < MC_ENGINE_AUTO || cfg->engine > MC_ENGINE_TILED) return fail(MC_ERR_ARG, "unknown engine");
@@ -253,9 +255,12 @@ int params_from_config(const mc_config *cfg, mc::ModelParams &p)
     return MC_OK;
 }
 
-int upload(mc_net *nt, const mc_config *cfg)
+// Allocate and fill the device store.  With `segs`, the synapses are drawn and
+// sorted on the GPU (the host holds only the plan), and the host gets the row
+// pointers and the ring depth back.
+int upload(mc_net *nt, const mc_config *cfg, const std::vector<mc::SynSeg> *segs)
 {
-    const mc::HostNet &H = nt->host;
+    mc::HostNet &H = nt->host;
     const int64_t N = H.n, M = H.m;
     int rc;
     HIP_TRY(hipGetDevice(&nt->device));
@@ -276,18 +281,33 @@ int upload(mc_net *nt, const mc_config *cfg)
         HIP_TRY(hipEventCreateWithFlags(&nt->snap_ev[b], hipEventDisableTiming));
     }
 
-    if ((rc = dalloc(&nt->u, N)) || (rc = dalloc(&nt->cur, N)) || (rc = dalloc(&nt->refr, N)) ||
-        (rc = dalloc(&nt->meta, N)) || (rc = dalloc(&nt->inst_off, H.n_inst + 1)) ||
-        (rc = dalloc(&nt->seeds, H.n_inst)) || (rc = dalloc(&nt->cdc, mc::kPops)) ||
-        (rc = dalloc(&nt->pois_thr, mc::kPops * mc::kPoisMax)) ||
-        (rc = dalloc(&nt->ring, static_cast<size_t>(H.ring) * N)) || (rc = dalloc(&nt->row_ptr, N + 1)) ||
-        (rc = dalloc(&nt->tgt, M)) || (rc = dalloc(&nt->dly, M)) || (rc = dalloc(&nt->ctl, 1)))
-        return rc;
+    if ((rc = dalloc(&nt->row_ptr, N + 1)) || (rc = dalloc(&nt->tgt, M)) || (rc = dalloc(&nt->dly, M))) return rc;
     const size_t wbytes = nt->params.wfmt == mc::kWFp32 ? 4 : 2;
     {
         hipError_t e = hipMalloc(&nt->w, std::max<size_t>(1, M * wbytes));
         if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
+    if (segs) {
+        int max_d = 1;
+        int64_t max_in_abs = 0;
+        std::string msg;
+        rc = mc::build_synapses_on_device(nt->params, H, *segs, nt->row_ptr, nt->tgt, nt->dly, nt->w, nt->stream, max_d,
+                                          max_in_abs, msg);
+        if (rc) return fail(rc, msg);
+        if (max_in_abs + static_cast<int64_t>(mc::kPoisMax) * std::llabs(static_cast<long long>(nt->sc.wq_ext)) >=
+            (int64_t{1} << 31))
+            return fail(MC_ERR_OVERFLOW_BOUND, "int32 input-buffer overflow bound exceeded");
+        H.ring = 2;
+        while (H.ring < max_d + 1) H.ring *= 2;
+        H.row_ptr.resize(static_cast<size_t>(N) + 1);
+        HIP_TRY(hipMemcpy(H.row_ptr.data(), nt->row_ptr, (N + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    }
+    if ((rc = dalloc(&nt->u, N)) || (rc = dalloc(&nt->cur, N)) || (rc = dalloc(&nt->refr, N)) ||
+        (rc = dalloc(&nt->meta, N)) || (rc = dalloc(&nt->inst_off, H.n_inst + 1)) ||
+        (rc = dalloc(&nt->seeds, H.n_inst)) || (rc = dalloc(&nt->cdc, mc::kPops)) ||
+        (rc = dalloc(&nt->pois_thr, mc::kPops * mc::kPoisMax)) ||
+        (rc = dalloc(&nt->ring, static_cast<size_t>(H.ring) * N)) || (rc = dalloc(&nt->ctl, 1)))
+        return rc;
     const int64_t work_cap = N + (M + 63) / 64 + 1;
     if ((rc = dalloc(&nt->work, work_cap))) return rc;
     nt->pois_slots = (N + 63) / 64 + 1;
@@ -311,8 +331,8 @@ int upload(mc_net *nt, const mc_config *cfg)
     HIP_TRY(hipMemcpy(nt->seeds, H.seeds.data(), H.n_inst * sizeof(uint64_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(nt->cdc, nt->sc.cdc, sizeof(nt->sc.cdc), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(nt->pois_thr, nt->sc.pois_thr, sizeof(nt->sc.pois_thr), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(nt->row_ptr, H.row_ptr.data(), (N + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
-    if (M) {
+    if (!segs) HIP_TRY(hipMemcpy(nt->row_ptr, H.row_ptr.data(), (N + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
+    if (M && !segs) {
         HIP_TRY(hipMemcpy(nt->tgt, H.tgt.data(), M * sizeof(int32_t), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(nt->dly, H.d.data(), M, hipMemcpyHostToDevice));
         if (nt->params.wfmt == mc::kWFp32) {
@@ -508,8 +528,10 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
     if (rc) { release(nt); return rc; }
     mc::derive_constants(nt->params, nt->sc);
     std::string msg;
+    std::vector<mc::SynSeg> segs;
     try {
-        rc = mc::build_host_network(nt->params, seeds, scales, n, nt->host, msg);
+        rc = cfg->device_build ? mc::plan_network(nt->params, seeds, scales, n, nt->host, segs, msg)
+                               : mc::build_host_network(nt->params, seeds, scales, n, nt->host, msg);
     } catch (const std::bad_alloc &) {
         rc = MC_ERR_NOMEM;
         msg = "out of host memory";
@@ -518,7 +540,7 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
         msg = "network build failed";
     }
     if (rc) { release(nt); return fail(rc, msg); }
-    rc = upload(nt, cfg);
+    rc = upload(nt, cfg, cfg->device_build ? &segs : nullptr);
     if (rc) { release(nt); return rc; }
     // Keep only what the host needs after upload.
     std::vector<int32_t>().swap(nt->host.tgt);

@@ -17,28 +17,15 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "philox_dev.hpp"
 
 namespace mc {
 namespace {
 
-constexpr uint64_t kMulA = 0xD2E7470EE14C6C93ULL, kMulB = 0xCA5A826395121157ULL;
-constexpr uint64_t kBumpA = 0x9E3779B97F4A7C15ULL, kBumpB = 0xBB67AE8584CAA73BULL;
-
 // Philox4x64-10 block for counter (c0, c1, 0, tag), key (seed, 0).
 __device__ __forceinline__ void philox_block(uint64_t c0, uint64_t c1, uint64_t tag, uint64_t seed, uint64_t out[4])
 {
-    uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = tag;
-    uint64_t k0 = seed, k1 = 0;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t a_lo = kMulA * x0, a_hi = __umul64hi(kMulA, x0);
-        const uint64_t b_lo = kMulB * x2, b_hi = __umul64hi(kMulB, x2);
-        const uint64_t y0 = b_hi ^ x1 ^ k0;
-        const uint64_t y2 = a_hi ^ x3 ^ k1;
-        x0 = y0; x1 = b_lo; x2 = y2; x3 = a_lo;
-        k0 += kBumpA; k1 += kBumpB;
-    }
-    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+    philox4x64(c0, c1, 0, tag, seed, out);
 }
 
 // 32-bit half h (0..7) of a block: high then low half of words 0, 1, 2, 3.

@@ -59,9 +59,22 @@ struct HostNet {
 
 void derive_constants(const ModelParams &p, StepConstants &c);
 
+// The synapses of one (instance, pre population a, post population b) pair:
+// global synapse indices [first, first + count), drawn with counter
+// (index - first, 8a + b, 0, kTagSyn) and key (seed of the instance, 0).
+struct SynSeg {
+    int32_t inst, a, b;
+    int64_t first, count;
+};
+
 // Build one or more instances.  Returns 0 or an MC_ERR_* code with msg set.
 int build_host_network(const ModelParams &p, const uint64_t *seeds, const double *scales,
                        int32_t n_inst, HostNet &out, std::string &msg);
+
+// Everything but the synapses: sizes, per-pair counts (as segments), neuron
+// metadata and initial state.  H.row_ptr, tgt, wq, w16, d and ring stay empty.
+int plan_network(const ModelParams &p, const uint64_t *seeds, const double *scales, int32_t n_inst, HostNet &H,
+                 std::vector<SynSeg> &segs, std::string &msg);
 
 // Reduced-precision rounding (round-to-nearest-even from double), as bit patterns.
 uint16_t half_bits_rne(double x);

@@ -180,8 +180,8 @@ void derive_constants(const ModelParams &p, StepConstants &c)
 }
 
 // ---- network ------------------------------------------------------------------
-int build_host_network(const ModelParams &p, const uint64_t *seeds, const double *scales, int32_t n_inst,
-                       HostNet &out, std::string &msg)
+int plan_network(const ModelParams &p, const uint64_t *seeds, const double *scales, int32_t n_inst, HostNet &out,
+                 std::vector<SynSeg> &segs, std::string &msg)
 {
     if (n_inst < 1) { msg = "at least one instance is required"; return MC_ERR_ARG; }
     for (int q = 0; q < 64; ++q)
@@ -237,17 +237,37 @@ int build_host_network(const ModelParams &p, const uint64_t *seeds, const double
     }
 
     // Enumerate (instance, pair) segments of the global synapse index space.
-    struct Seg { int32_t inst, a, b; int64_t first, count; };
-    std::vector<Seg> segs;
+    segs.clear();
     {
         int64_t at = 0;
         for (int j = 0; j < n_inst; ++j)
             for (int q = 0; q < 64; ++q) {
                 const int64_t k = pair_k[static_cast<size_t>(j) * 64 + q];
-                if (k) segs.push_back(Seg{j, q / 8, q % 8, at, k});
+                if (k) segs.push_back(SynSeg{j, q / 8, q % 8, at, k});
                 at += k;
             }
     }
+
+    // Initial membrane potentials u ~ U[0, theta) (or zero).
+    H.u0.assign(n_total, 0.0f);
+    if (p.init_mode == 0) {
+        for (int j = 0; j < n_inst; ++j)
+            for (int32_t i = H.inst_off[j]; i < H.inst_off[j + 1]; ++i) {
+                const Block4 x = philox_host(static_cast<uint64_t>(i - H.inst_off[j]), 0, 0, kTagInit, H.seeds[j]);
+                H.u0[i] = static_cast<float>(p.theta_mv * unit_open_high(x.v[0]));
+            }
+    }
+    return MC_OK;
+}
+
+int build_host_network(const ModelParams &p, const uint64_t *seeds, const double *scales, int32_t n_inst,
+                       HostNet &out, std::string &msg)
+{
+    std::vector<SynSeg> segs;
+    int rc = plan_network(p, seeds, scales, n_inst, out, segs, msg);
+    if (rc) return rc;
+    HostNet &H = out;
+    const int64_t n_total = H.n, m_total = H.m;
     auto seg_of = [&segs](int64_t s) {
         size_t lo = 0, hi = segs.size();
         while (hi - lo > 1) {
@@ -257,7 +277,7 @@ int build_host_network(const ModelParams &p, const uint64_t *seeds, const double
         return lo;
     };
 
-    auto pre_of = [&](const Seg &sg, const Block4 &x) {
+    auto pre_of = [&](const SynSeg &sg, const Block4 &x) {
         const int32_t *po = &H.pop_off[static_cast<size_t>(sg.inst) * (kPops + 1)];
         return po[sg.a] + static_cast<int32_t>(scale_to(x.v[0], po[sg.a + 1] - po[sg.a]));
     };
@@ -270,7 +290,7 @@ int build_host_network(const ModelParams &p, const uint64_t *seeds, const double
         size_t g = seg_of(s0);
         for (int64_t s = s0; s < s1; ++s) {
             while (s >= segs[g].first + segs[g].count) ++g;
-            const Seg &sg = segs[g];
+            const SynSeg &sg = segs[g];
             const Block4 x = philox_host(static_cast<uint64_t>(s - sg.first), static_cast<uint64_t>(8 * sg.a + sg.b), 0,
                                          kTagSyn, H.seeds[sg.inst]);
             fill[pre_of(sg, x) + 1].fetch_add(1, std::memory_order_relaxed);
@@ -290,7 +310,7 @@ int build_host_network(const ModelParams &p, const uint64_t *seeds, const double
         size_t g = seg_of(s0);
         for (int64_t s = s0; s < s1; ++s) {
             while (s >= segs[g].first + segs[g].count) ++g;
-            const Seg &sg = segs[g];
+            const SynSeg &sg = segs[g];
             const int32_t *po = &H.pop_off[static_cast<size_t>(sg.inst) * (kPops + 1)];
             const Block4 x = philox_host(static_cast<uint64_t>(s - sg.first), static_cast<uint64_t>(8 * sg.a + sg.b), 0,
                                          kTagSyn, H.seeds[sg.inst]);
@@ -370,16 +390,6 @@ int build_host_network(const ModelParams &p, const uint64_t *seeds, const double
             if (in_abs[i] + pois_max >= (int64_t{1} << 31)) {
                 msg = "int32 input-buffer overflow bound exceeded";
                 return MC_ERR_OVERFLOW_BOUND;
-            }
-    }
-
-    // Initial membrane potentials u ~ U[0, theta) (or zero).
-    H.u0.assign(n_total, 0.0f);
-    if (p.init_mode == 0) {
-        for (int j = 0; j < n_inst; ++j)
-            for (int32_t i = H.inst_off[j]; i < H.inst_off[j + 1]; ++i) {
-                const Block4 x = philox_host(static_cast<uint64_t>(i - H.inst_off[j]), 0, 0, kTagInit, H.seeds[j]);
-                H.u0[i] = static_cast<float>(p.theta_mv * unit_open_high(x.v[0]));
             }
     }
     return MC_OK;
