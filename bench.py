@@ -382,7 +382,8 @@ def main():
                    "conn_table": standin_description(),
                    "engine": "tiled" if tiled else "graph", "tile": info["tile_neurons"],
                    "n_tiles": info["n_tiles"], "ring_depth": info["ring_depth"],
-                   "poll_delay": info["poll_delay"] if tiled else None},
+                   "poll_delay": info["poll_delay"] if tiled else None,
+                   "lds_window": info["lds_window"] if tiled else None},
         "events_per_s": round(events / wall, 1),
         **({"step_budget_us": args.step_budget,
             "dropped_events_frac": round((c1["dropped_events"] - c0["dropped_events"]) / max(1, events), 6)}

@@ -135,6 +135,9 @@ typedef struct mc_info {
                                     TILED 8, or 4 for FP16/BF16 tiles of <= 1024 neurons */
     int32_t poll_delay;          /* TILED engine: sleep before a step's first poll of the
                                     other tiles' words, units of 64 clocks */
+    int32_t lds_window;          /* TILED engine with the ring in global memory: slots n+1 ..
+                                    n+lds_window also kept in LDS (events with delays up to
+                                    it are added there); 0 otherwise */
 } mc_info;
 
 /* Launch knobs chosen by the autotuner or set by hand (0 = keep current). */

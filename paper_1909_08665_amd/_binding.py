@@ -51,7 +51,7 @@ class McInfo(C.Structure):
                 ("n_neurons", C.c_int64), ("n_synapses", C.c_int64), ("tile_neurons", C.c_int32),
                 ("n_tiles", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
                 ("deliver_grid", C.c_int32), ("lds_ring", C.c_int32), ("syn_bytes", C.c_int32),
-                ("poll_delay", C.c_int32)]
+                ("poll_delay", C.c_int32), ("lds_window", C.c_int32)]
 
 
 class McLaunch(C.Structure):

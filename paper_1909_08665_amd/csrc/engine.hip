@@ -421,6 +421,13 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
         sh = mc::tiled_shape(tile_max, max_intiles, nt->host.ring, false);
         if (sh.lds + lds_static > 160 * 1024) return fail(MC_ERR_UNSUPPORTED, "tile scratch does not fit in LDS");
     }
+    if (!sh.lds_ring) {
+        // the LDS left over holds a window of the nearest slots (delays up to win)
+        const size_t used = lds_static + sh.lds + 8;
+        const size_t room = used < 160 * 1024 ? 160 * 1024 - used : 0;
+        const int win = static_cast<int>(std::min<size_t>(nt->host.ring - 1, room / (4 * static_cast<size_t>(tile_max))));
+        sh = mc::tiled_shape(tile_max, max_intiles, nt->host.ring, false, win);
+    }
     int per_cu = 0;
     HIP_TRY(mc::tiled_max_coresident(sf, sh, &per_cu));
     if (static_cast<int64_t>(per_cu) * nt->n_cu < T)
@@ -705,6 +712,7 @@ int run_tiled(mc_net *nt, int64_t steps)
     tn.syn_fmt = nt->syn_fmt;
     tn.xchg = nt->xchg;
     tn.poll_delay = nt->poll_delay;
+    tn.win = nt->tiled_shape.win;
     tn.xent = nt->xent;
     tn.abort = nt->abort_flag;
     // Entry words are tagged with their step.  After the step index went back
@@ -1281,6 +1289,7 @@ int mc_get_info(mc_net *net, mc_info *out)
     out->block = net->block;
     out->deliver_grid = net->deliver_grid;
     out->poll_delay = net->poll_delay;
+    out->lds_window = net->engine == MC_ENGINE_TILED ? net->tiled_shape.win : 0;
     return MC_OK;
 }
 

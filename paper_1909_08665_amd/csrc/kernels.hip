@@ -505,13 +505,18 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     const int32_t t0 = td.t0;
     const int tlen = td.len;
 
-    int *ring = lds;                                   // [R][tmax] when LRING
-    // global-ring variant: this workgroup's private, cache-line aligned slice
+    // Global-ring variant: the ring lives in this workgroup's private, cache-line
+    // aligned slice of global memory, and the nearest W slots also have an LDS
+    // row each: an event whose delay is at most W is added there, and the update
+    // sums both parts of its slot.  At step n (after its update) the window rows
+    // hold slots n + 1 .. n + W, slot s in row s mod W.
+    const int W = LRING ? 0 : P.win;
+    int *ring = lds;                                   // [R][tmax] when LRING, else the [W][tmax] window
     int32_t *gring = LRING ? nullptr : P.gring + static_cast<size_t>(t) * R * P.gstride;
     // [2][tmax/8 + 2][4] Philox blocks of steps n + 1 and n + 2 (by step parity),
-    // one per group of 8 neurons (R * tmax is even: 8-byte aligned)
+    // one per group of 8 neurons (8-byte aligned: the ring part is rounded to even)
     const int nbk = tmax / 8 + 2;
-    uint64_t *s_blk = reinterpret_cast<uint64_t *>(lds + (LRING ? R * tmax : 0));
+    uint64_t *s_blk = reinterpret_cast<uint64_t *>(lds + (LRING ? R * tmax : ((W * tmax + 1) & ~1)));
     int *s_cnt = reinterpret_cast<int *>(s_blk + 2 * 4 * nbk);   // [T + 1] spike counts -> offsets
     int *s_first = s_cnt + P.max_intiles + 1;          // [T] first spike id of each tile (valid if it spiked)
     int *s_ids = s_first + P.max_intiles;              // [kSpkBatch]
@@ -528,6 +533,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             for (int q = l; q < tlen; q += nthr) gring[s * P.gstride + q] = B.ring[static_cast<size_t>(s) * B.n + t0 + q];
         }
     }
+    for (int q = l; q < W * tmax; q += nthr) ring[q] = 0;
     if (l == 0) s_abort = 0;
 
     // The tile lies in one instance: its seed and local numbering are uniform.
@@ -603,6 +609,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         uint32_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
         uint64_t *entries = P.xent + (static_cast<size_t>(par) * P.n_tiles + td.itile0) * tmax;
         const int slot = static_cast<int>(n & mask);
+        const int wslot = W ? static_cast<int>(n % W) : 0;
         const uint64_t t_step = BUDGET ? __builtin_amdgcn_s_memrealtime() : 0;
         tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
         uint64_t *tr_blk = (P.trace && l == nthr - 1 && s < P.trace_steps)
@@ -625,6 +632,11 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                     int32_t *cell = gring + slot * P.gstride + q;
                     inq = *cell;
                     *cell = 0;
+                    if (W) {
+                        int *wc = ring + wslot * tmax + q;
+                        inq += *wc;
+                        *wc = 0;
+                    }
                 }
                 inq += kp[k] * B.wq_ext;
                 pois_sum += static_cast<unsigned long long>(kp[k]);
@@ -750,11 +762,16 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 P.syn, s_beg, s_pre, nb, E,
                 [&](int tg, int d, int wq) {
                     const int ds = static_cast<int>((n + d) & mask);
-                    if (LRING)
+                    if (LRING) {
                         atomicAdd(ring + ds * tmax + tg, wq);
-                    else
+                    } else if (d <= W) {
+                        int row = wslot + d;
+                        if (row >= W) row -= W;
+                        atomicAdd(ring + row * tmax + tg, wq);
+                    } else {
                         __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                 },
                 t_step, BUDGET ? P.budget_ticks : 0u, &drop_acc);
             __syncthreads();
@@ -775,9 +792,24 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         }
     }
     __syncthreads();
+    // the window rows hold slots n .. n + W - 1 (n: the next step)
+    const int n_slot = static_cast<int>(n & mask), n_row = W ? static_cast<int>(n % W) : 0;
     for (int s2 = 0; s2 < R; ++s2)
-        for (int q = l; q < tlen; q += nthr)
-            B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = LRING ? ring[s2 * tmax + q] : gring[s2 * P.gstride + q];
+        for (int q = l; q < tlen; q += nthr) {
+            int v;
+            if (LRING) {
+                v = ring[s2 * tmax + q];
+            } else {
+                v = gring[s2 * P.gstride + q];
+                const int k = (s2 - n_slot) & mask;
+                if (k < W) {
+                    int row = n_row + k;
+                    if (row >= W) row -= W;
+                    v += ring[row * tmax + q];
+                }
+            }
+            B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = v;
+        }
     unsigned long long ps = pois_sum, dr = drop_acc;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -879,14 +911,16 @@ const void *tiled_kernel(int sf, bool lr, int npt, bool budget)
 
 }  // namespace
 
-TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring)
+TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring, int win)
 {
     TiledShape sh{};
     sh.lds_ring = lds_ring;
+    sh.win = lds_ring ? 0 : win;
     sh.npt = tile_max <= 1024 ? 1 : tile_max <= 2048 ? 2 : 4;
     const int per_thread = (tile_max + sh.npt - 1) / sh.npt;
     sh.threads = ((per_thread + 63) / 64) * 64;
-    sh.lds = sizeof(int) * ((lds_ring ? static_cast<size_t>(ring) * tile_max : 0) + 16 * (static_cast<size_t>(tile_max) / 8 + 2) +
+    const size_t ring_ints = lds_ring ? static_cast<size_t>(ring) * tile_max : ((static_cast<size_t>(sh.win) * tile_max + 1) & ~size_t{1});
+    sh.lds = sizeof(int) * (ring_ints + 16 * (static_cast<size_t>(tile_max) / 8 + 2) +
                             (2 * static_cast<size_t>(max_intiles) + 1) + 3 * kSpkBatch + 1 + tile_max);
     return sh;
 }

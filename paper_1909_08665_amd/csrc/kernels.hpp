@@ -96,7 +96,7 @@ struct TiledNet {
     int32_t gstride;                  // global-ring variant: ints per slot row (multiple of 32)
     unsigned long long *dropped;      // [n_tiles] events dropped by the step budget (this launch)
     uint32_t budget_ticks;            // step budget in 100 MHz clock ticks; 0: none
-    int32_t pad3;
+    int32_t win;                      // global-ring variant: LDS window of the nearest `win` slots (< R)
     int32_t *gring;                   // global-ring variant: [n_tiles][R][gstride], one slice per workgroup
 };
 
@@ -116,9 +116,10 @@ struct TiledShape {
     bool lds_ring;
     int npt;
     int threads;
+    int win;                          // global-ring variant: LDS window rows
     size_t lds;                       // dynamic LDS bytes
 };
-TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring);
+TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring, int win = 0);
 hipError_t launch_tiled(const TiledNet &t, const TiledShape &sh, int64_t steps, hipStream_t st);
 hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_cu);
 // Spike injection (external stimulation): deliver the rows of `ids` as if they

@@ -188,6 +188,24 @@ def test_batch_instances_equal_single_runs(conn):
         assert tot["max_spikes_per_step"] >= max(net.counters(j)["max_spikes_per_step"] for j in range(4))
 
 
+def test_global_ring_with_partial_lds_window(conn):
+    """Tiles of up to 4096 neurons with the ring in global memory: the LDS left
+    over holds only a few of the nearest slots, so events go to both the LDS
+    window (short delays) and the global slice (long delays)."""
+    seeds, scales = [121, 122], [0.05, 0.05]
+    _say("partial lds window")
+    net = mc.Network.build_batch(seeds, scales, conn)
+    net.set_launch(engine=mc.ENGINE_TILED, tile=4096, ring=2)
+    info = net.info()
+    assert info["lds_ring"] == 0 and 1 <= info["lds_window"] < 20, info
+    for chunk in (700, 500):              # two launches: the window is written back and reloaded
+        net.run(chunk)
+    for j, (s, sc) in enumerate(zip(seeds, scales)):
+        orc = _oracle(s, sc, conn)
+        orc.run(1200)
+        assert _same_run(net, orc, inst=j) > 0
+
+
 def test_batch_segments_with_many_spikes(conn):
     """Several 10-15 % instances over 3000 steps: recorder segments of 10^5+
     spikes, drained on the host while the next segment runs, in parallel

@@ -60,7 +60,12 @@ def test_missing_table_and_bad_args_rejected():
         mc.Network.build(1, 0.02, conn, wfmt=7)
     with pytest.raises(mc.MCError):
         mc.Network.build(1, 0.02, conn, tau_syn_ms=10.0)
+    with pytest.raises(mc.MCError):
+        mc.Network.build(1, 0.02, conn, device_build=2)
     assert L.mc_run(None, 1) == -1
+    assert L.mc_set_step_budget(None, 5.0) == -1
+    assert L.mc_set_launch(None, None) == -1
+    assert L.mc_inject_spikes(None, 0, None, 0, None) == -1
     L.mc_free(None)
 
 
