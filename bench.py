@@ -31,14 +31,15 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seed, scale, conn, warm, steps):
+def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None):
     """The oracle (FP32 mirror) on this host's cores, on a bounded sample of the
     same workload: same network, `steps` steps after `warm` untimed steps."""
     from oracle import oracle as O
 
     cores = O.max_threads()
     t = time.time()
-    net = O.OracleNet.build(seed, scale, conn.reshape(64))
+    params = O.default_params() if i_dc is None else O.default_params(poisson_on=False, i_dc=i_dc)
+    net = O.OracleNet.build(seed, scale, conn.reshape(64), params)
     log(f"oracle build {time.time() - t:.1f}s ({cores} threads)")
     net.run(warm)
     net.spikes(clear=True)
@@ -234,6 +235,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--device-build", action="store_true", help="draw and sort the synapse store on the GPU")
+    ap.add_argument("--dc", action="store_true",
+                    help="DC-input workload: no Poisson background, each population driven by the mean "
+                         "current of its Poisson drive (stand-in amplitudes)")
     ap.add_argument("--step-budget", type=float, default=0, metavar="US",
                     help="lossy real-time mode: drop deliveries past US microseconds into a step (tiled engine)")
     ap.add_argument("--poll-delay", type=int, default=0,
@@ -261,7 +265,7 @@ def main():
     import torch
 
     import paper_1909_08665_amd as mc
-    from synth_inputs import standin_conn_table, standin_description
+    from synth_inputs import dc_standin_amplitudes, standin_conn_table, standin_description
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -284,10 +288,12 @@ def main():
     n_inst = len(seeds)
     t = time.time()
     db = int(args.device_build)
+    drive = dict(poisson_on=False, i_dc=dc_standin_amplitudes()) if args.dc else {}
     if n_inst == 1:
-        net = mc.Network.build(seeds[0], scales[0], conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db)
+        net = mc.Network.build(seeds[0], scales[0], conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db, **drive)
     else:
-        net = mc.Network.build_batch(seeds, scales, conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db)
+        net = mc.Network.build_batch(seeds, scales, conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db,
+                                     **drive)
     if args.tile:
         net.set_launch(engine=mc.ENGINE_TILED, tile=args.tile)
     if args.poll_delay:
@@ -377,7 +383,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"microcircuit scale {scales[0]} " if n_inst == 1 else CONFIGS[args.config] + " ")
                                + f"({n_neurons} neurons, {n_syn} synapses), {args.wfmt.upper()} weight store, "
-                               f"{args.steps * DT_S:g} s biological time, Poisson background, dt 0.1 ms",
+                               f"{args.steps * DT_S:g} s biological time, "
+                               + ("DC input (per population the mean current of its Poisson drive)"
+                                  if args.dc else "Poisson background") + ", dt 0.1 ms",
                    "instances": n_inst, "seed": seeds[0] if n_inst == 1 else [seeds[0], seeds[-1]],
                    "conn_table": standin_description(),
                    "engine": "tiled" if tiled else "graph", "tile": info["tile_neurons"],
@@ -398,7 +406,8 @@ def main():
     net.close()
     if not args.no_cpu_baseline:
         # one instance of the workload (the first) on the host cores, scaled to the batch
-        cb = cpu_baseline(seeds[0], scales[0], conn, args.cpu_warm, args.cpu_steps)
+        cb = cpu_baseline(seeds[0], scales[0], conn, args.cpu_warm, args.cpu_steps,
+                          i_dc=dc_standin_amplitudes() if args.dc else None)
         if n_inst > 1:
             cb["sample"] += f"; instance 0 of {n_inst} (per-instance rate)"
         out["cpu_baseline"] = cb

@@ -1,9 +1,10 @@
-"""Seeded workload descriptions: uneven batch scales and forced spike lists."""
+"""Seeded workload descriptions: uneven batch scales, forced spike lists and
+the stand-in amplitudes of the DC-input workload."""
 from __future__ import annotations
 
 import numpy as np
 
-from .conn_table import FULL_SIZE
+from .conn_table import FULL_SIZE, K_EXT
 
 
 def batch_scales(n: int, lo: float, hi: float, seed: int):
@@ -20,3 +21,11 @@ def forced_spike_list(count: int, scale: float, seed: int):
     rng = np.random.Generator(np.random.Philox(seed))
     count = min(int(count), total)
     return np.sort(rng.choice(total, size=count, replace=False)).astype(np.int32)
+
+
+def dc_standin_amplitudes(nu_bg_hz: float = 8.0, w_ext_pa: float = 87.8, tau_syn_ms: float = 0.5):
+    """Per-population DC input (pA) standing in for the amplitudes the paper's
+    DC-driven workload does not give: the mean current the population's
+    Poisson background would inject through the exponential synapse,
+    K_ext * nu_bg * w_ext * tau_syn (rate times charge per spike)."""
+    return tuple(k * nu_bg_hz * w_ext_pa * tau_syn_ms * 1e-3 for k in K_EXT)

@@ -224,6 +224,21 @@ def test_batch_segments_with_many_spikes(conn):
     assert total > 100000
 
 
+@pytest.mark.parametrize("scale", [0.02, 0.1])
+def test_dc_workload_parity(conn, scale):
+    """The DC-input workload (no Poisson background; each population driven by
+    the mean current of its Poisson drive) equals the oracle."""
+    from synth_inputs import dc_standin_amplitudes
+    _say("dc workload", scale)
+    i_dc = dc_standin_amplitudes()
+    net = mc.Network.build(9, scale, conn, poisson_on=False, i_dc=i_dc)
+    orc = _oracle(9, scale, conn, poisson_on=False, i_dc=i_dc)
+    net.run(1500)
+    orc.run(1500)
+    assert _same_run(net, orc) > 0
+    assert net.counters()["poisson_events"] == 0
+
+
 def test_dc_input_hook_parity(conn):
     _say("dc input")
     i_dc = [420.0, 380.0, 500.0, 0.0, 650.0, 390.0, 0.0, 800.0]
