@@ -484,11 +484,14 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return base + b / kXcds;
 }
 
-// BUDGET: the lossy real-time form (P.budget_ticks > 0); a separate
-// instantiation, so that the step kernel without a budget carries none of it.
-template <int SF, bool LRING, int NPT, bool BUDGET>
+// MODE bit 0: the lossy real-time form (P.budget_ticks > 0); bit 1: the
+// per-step phase trace (P.trace set).  Separate instantiations, so that the
+// plain step kernel carries none of their state (each costs it ~3 % in scalar
+// register pressure).
+template <int SF, bool LRING, int NPT, int MODE>
 __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
 {
+    constexpr bool BUDGET = (MODE & 1) != 0, TRACE = (MODE & 2) != 0;
     extern __shared__ int lds[];
     __shared__ uint64_t s_thr[8 * kPoisMaxDev];
     __shared__ int s_wave[17];
@@ -611,8 +614,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         const int slot = static_cast<int>(n & mask);
         const int wslot = W ? static_cast<int>(n % W) : 0;
         const uint64_t t_step = BUDGET ? __builtin_amdgcn_s_memrealtime() : 0;
-        tr = (P.trace && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
-        uint64_t *tr_blk = (P.trace && l == nthr - 1 && s < P.trace_steps)
+        tr = (TRACE && l == 0 && s < P.trace_steps) ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots
+                                                      : nullptr;
+        uint64_t *tr_blk = (TRACE && l == nthr - 1 && s < P.trace_steps)
                                ? P.trace + (static_cast<size_t>(s) * P.n_tiles + t) * kTraceSlots : nullptr;
         if (tr) tr[0] = __builtin_amdgcn_s_memrealtime();
         // ---- 1. neuron update ------------------------------------------------
@@ -880,32 +884,37 @@ __global__ void k_pack_synapses(const int32_t *tgt, const uint8_t *dly, const vo
 }
 
 template <int SF, bool LR, int NPT>
-const void *tiled_fn3(bool budget)
+const void *tiled_fn3(int mode)
 {
-    return budget ? reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, true>)
-                  : reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, false>);
+    switch (mode) {
+    case 0: return reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, 0>);
+    case 1: return reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, 1>);
+    case 2: return reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, 2>);
+    default: return reinterpret_cast<const void *>(&k_tiled<SF, LR, NPT, 3>);
+    }
 }
 
 template <int SF, bool LR>
-const void *tiled_fn2(int npt, bool budget)
+const void *tiled_fn2(int npt, int mode)
 {
-    return npt == 1 ? tiled_fn3<SF, LR, 1>(budget) : npt == 2 ? tiled_fn3<SF, LR, 2>(budget) : tiled_fn3<SF, LR, 4>(budget);
+    return npt == 1 ? tiled_fn3<SF, LR, 1>(mode) : npt == 2 ? tiled_fn3<SF, LR, 2>(mode) : tiled_fn3<SF, LR, 4>(mode);
 }
 
 template <int SF>
-const void *tiled_fn1(bool lr, int npt, bool budget)
+const void *tiled_fn1(bool lr, int npt, int mode)
 {
-    return lr ? tiled_fn2<SF, true>(npt, budget) : tiled_fn2<SF, false>(npt, budget);
+    return lr ? tiled_fn2<SF, true>(npt, mode) : tiled_fn2<SF, false>(npt, mode);
 }
 
-const void *tiled_kernel(int sf, bool lr, int npt, bool budget)
+// mode: bit 0 step budget, bit 1 phase trace
+const void *tiled_kernel(int sf, bool lr, int npt, int mode)
 {
     switch (sf) {
-    case kSyn8F32: return tiled_fn1<kSyn8F32>(lr, npt, budget);
-    case kSyn8F16: return tiled_fn1<kSyn8F16>(lr, npt, budget);
-    case kSyn8BF16: return tiled_fn1<kSyn8BF16>(lr, npt, budget);
-    case kSyn4F16: return tiled_fn1<kSyn4F16>(lr, npt, budget);
-    default: return tiled_fn1<kSyn4BF16>(lr, npt, budget);
+    case kSyn8F32: return tiled_fn1<kSyn8F32>(lr, npt, mode);
+    case kSyn8F16: return tiled_fn1<kSyn8F16>(lr, npt, mode);
+    case kSyn8BF16: return tiled_fn1<kSyn8BF16>(lr, npt, mode);
+    case kSyn4F16: return tiled_fn1<kSyn4F16>(lr, npt, mode);
+    default: return tiled_fn1<kSyn4BF16>(lr, npt, mode);
     }
 }
 
@@ -927,10 +936,10 @@ TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring, i
 
 hipError_t tiled_max_coresident(int syn_fmt, const TiledShape &sh, int *blocks_per_cu)
 {
-    // both forms (with and without a step budget) must fit
+    // every form (step budget, phase trace) must fit
     *blocks_per_cu = 1 << 30;
-    for (bool budget : {false, true}) {
-        const void *f = tiled_kernel(syn_fmt, sh.lds_ring, sh.npt, budget);
+    for (int mode = 0; mode < 4; ++mode) {
+        const void *f = tiled_kernel(syn_fmt, sh.lds_ring, sh.npt, mode);
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
         if (e != hipSuccess) return e;
         int b = 0;
@@ -965,7 +974,8 @@ hipError_t launch_tiled(const TiledNet &tn, const TiledShape &sh, int64_t steps,
     TiledNet arg = tn;
     int64_t nsteps = steps;
     void *args[] = {&arg, &nsteps};
-    return hipLaunchCooperativeKernel(tiled_kernel(tn.syn_fmt, sh.lds_ring, sh.npt, tn.budget_ticks != 0), dim3(tn.n_tiles),
+    const int mode = (tn.budget_ticks != 0 ? 1 : 0) | (tn.trace != nullptr ? 2 : 0);
+    return hipLaunchCooperativeKernel(tiled_kernel(tn.syn_fmt, sh.lds_ring, sh.npt, mode), dim3(tn.n_tiles),
                                       dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
 }
 
