@@ -103,7 +103,7 @@ struct mc_net {
     uint2 *subrow = nullptr;           // tiled engine: per-tile (first synapse, count) of each sub-row
     void *syn = nullptr;               // tiled engine: packed synapse records
     int32_t syn_fmt = 0;
-    uint32_t *xchg = nullptr;
+    uint64_t *xchg = nullptr;
     uint64_t *xent = nullptr;
     unsigned long long *dropped_acc = nullptr;   // [2][n_tiles], one half per recorder
     unsigned long long *h_dropped = nullptr;     // pinned copy
@@ -776,7 +776,7 @@ int run_tiled(mc_net *nt, int64_t steps)
         HIP_TRY(hipMemsetAsync(tn.dropped, 0, nt->n_tiles * sizeof(unsigned long long), nt->stream));
         // Tile words from an earlier launch carry older tags; clearing them rules out
         // a tag match across a jump of the step index (engine switch).
-        HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint32_t), nt->stream));
+        HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint64_t), nt->stream));
         HIP_TRY(hipMemsetAsync(nt->abort_flag, 0, sizeof(uint32_t), nt->stream));
         HIP_TRY(hipMemsetAsync(&nt->ctl->rec_total, 0, sizeof(int64_t), nt->stream));
         HIP_TRY(hipMemsetAsync(&nt->ctl->flags, 0, sizeof(uint32_t), nt->stream));

@@ -295,10 +295,13 @@ hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st)
 //   5. read this tile's sub-row of every spiking row and add the weights into
 //      the LDS ring with LDS integer atomics.
 //
-// Exchange protocol: each tile owns one 32-bit word per step parity,
-//     bits 31..30 tag ((n >> 1) & 1) + 1, 29..16 spike count,
-//     15..0 offset of the first spike in the tile,
-// and, for its 2nd, 3rd, ... spikes, 64-bit entry words (tag32 = n + 1 | id).
+// Exchange protocol: each tile owns one 64-bit word per step parity,
+//     bits 63..62 tag ((n >> 1) & 1) + 1, 61..48 spike count,
+//     47..0 the offsets in the tile (12 bits each, tiles <= 4096) of its
+//     first four spikes, first at bits 47..36,
+// and, for its 5th, 6th, ... spikes, 64-bit entry words (tag32 = n + 1 | id);
+// at full scale a tile almost never spikes more than four times in a step, so
+// a step's ids arrive with the words and no entry has to be read.
 // Words are written and polled with relaxed agent-scope atomics; a reader
 // accepts a word only when its tag matches, so no fence or counter is needed:
 // an aligned store is seen whole or not at all.  A tile cannot publish step
@@ -313,6 +316,7 @@ namespace mc {
 namespace {
 
 constexpr int kSpkBatch = 2048;              // spikes processed per delivery batch
+constexpr int kWordIds = 4;                  // spike offsets carried by a tile's word
 constexpr int kDeliverU = 4;                 // records in flight per thread in the step kernel's delivery
 constexpr int kInjectU = 8;                  // and in the injection kernel
 constexpr int kInjBatch = 2048;              // spikes per batch of the injection kernel
@@ -520,10 +524,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     // one per group of 8 neurons (8-byte aligned: the ring part is rounded to even)
     const int nbk = tmax / 8 + 2;
     uint64_t *s_blk = reinterpret_cast<uint64_t *>(lds + (LRING ? R * tmax : ((W * tmax + 1) & ~1)));
-    int *s_cnt = reinterpret_cast<int *>(s_blk + 2 * 4 * nbk);   // [T + 1] spike counts -> offsets
-    int *s_first = s_cnt + P.max_intiles + 1;          // [T] first spike id of each tile (valid if it spiked)
-    int *s_ids = s_first + P.max_intiles;              // [kSpkBatch]
-    int *s_beg = s_ids + kSpkBatch;                    // [kSpkBatch] sub-row start
+    uint64_t *s_word = s_blk + 2 * 4 * nbk;            // [T] this step's word of every tile of the instance
+    int *s_cnt = reinterpret_cast<int *>(s_word + P.max_intiles);   // [T + 1] spike counts -> offsets
+    int *s_beg = s_cnt + P.max_intiles + 1;            // [kSpkBatch] sub-row start
     int *s_pre = s_beg + kSpkBatch;                    // [kSpkBatch + 1] sub-row lengths -> offsets
     int *s_own = s_pre + kSpkBatch + 1;                // [tmax] this tile's spikes
 
@@ -607,9 +610,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     uint64_t *tr = nullptr;
     for (int64_t s = 0; s < steps; ++s, ++n) {
         const int par = static_cast<int>(n & 1);
-        const uint32_t tag2 = static_cast<uint32_t>((n >> 1) & 1) + 1u;
+        const uint64_t tag2 = static_cast<uint64_t>((n >> 1) & 1) + 1u;
         const uint64_t tag32 = static_cast<uint64_t>(static_cast<uint32_t>(n + 1));
-        uint32_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
+        uint64_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
         uint64_t *entries = P.xent + (static_cast<size_t>(par) * P.n_tiles + td.itile0) * tmax;
         const int slot = static_cast<int>(n & mask);
         const int wslot = W ? static_cast<int>(n % W) : 0;
@@ -668,14 +671,17 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             if (spike[k]) {
                 const int32_t i = t0 + l + k * nthr;
                 s_own[pos] = i;
-                if (pos > 0) store_word(entries + static_cast<size_t>(tl) * tmax + pos, (tag32 << 32) | static_cast<uint32_t>(i));
+                if (pos >= kWordIds)
+                    store_word(entries + static_cast<size_t>(tl) * tmax + pos, (tag32 << 32) | static_cast<uint32_t>(i));
                 ++pos;
             }
         }
         __syncthreads();
         if (l == 0) {
-            const uint32_t first = nspk ? static_cast<uint32_t>(s_own[0] - t0) : 0u;
-            store_word(words + tl, (tag2 << 30) | (static_cast<uint32_t>(nspk) << 16) | first);
+            uint64_t w = (tag2 << 62) | (static_cast<uint64_t>(nspk) << 48);
+            for (int k = 0; k < min(nspk, kWordIds); ++k)
+                w |= static_cast<uint64_t>(s_own[k] - t0) << (36 - 12 * k);
+            store_word(words + tl, w);
         }
         if (tr) tr[1] = __builtin_amdgcn_s_memrealtime();
         // ---- 3. background input: blocks of step n + 2 into the buffer whose
@@ -691,13 +697,13 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         if (l < T)
             for (int z = 0; z < P.poll_delay; ++z) __builtin_amdgcn_s_sleep(1);
         for (int q = l; q < T; q += nthr) {
-            uint32_t w = 0;
-            if (!wait_word(words + q, P.abort, ctl, [tag2](uint32_t x) { return (x >> 30) == tag2; }, w)) {
+            uint64_t w = 0;
+            if (!wait_word(words + q, P.abort, ctl, [tag2](uint64_t x) { return (x >> 62) == tag2; }, w)) {
                 s_abort = 1;
                 break;
             }
-            s_cnt[q] = static_cast<int>((w >> 16) & 0x3FFFu);
-            s_first[q] = td.inst_n0 + q * td.stride + static_cast<int>(w & 0xFFFFu);
+            s_cnt[q] = static_cast<int>((w >> 48) & 0x3FFFu);
+            s_word[q] = w;
         }
         __syncthreads();
         if (s_abort) break;
@@ -742,8 +748,8 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 const int g = b0 + q;
                 const int src = find_segment(s_cnt, T + 1, g);
                 const int k = g - s_cnt[src];
-                int pre = s_first[src];
-                if (k > 0) {
+                int pre = td.inst_n0 + src * td.stride + static_cast<int>((s_word[src] >> (36 - 12 * min(k, 3))) & 0xFFFu);
+                if (k >= kWordIds) {
                     uint64_t w = 0;
                     if (!wait_word(entries + static_cast<size_t>(src) * tmax + k, P.abort, ctl,
                                    [tag32](uint64_t x) { return (x >> 32) == tag32; }, w)) {
@@ -930,7 +936,7 @@ TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring, i
     sh.threads = ((per_thread + 63) / 64) * 64;
     const size_t ring_ints = lds_ring ? static_cast<size_t>(ring) * tile_max : ((static_cast<size_t>(sh.win) * tile_max + 1) & ~size_t{1});
     sh.lds = sizeof(int) * (ring_ints + 16 * (static_cast<size_t>(tile_max) / 8 + 2) +
-                            (2 * static_cast<size_t>(max_intiles) + 1) + 3 * kSpkBatch + 1 + tile_max);
+                            (3 * static_cast<size_t>(max_intiles) + 1) + 2 * kSpkBatch + 1 + tile_max);
     return sh;
 }
 

@@ -88,7 +88,7 @@ struct TiledNet {
     const void *syn;                  // packed synapse records (SynFmt), CSR order
     int32_t syn_fmt;
     int32_t poll_delay;               // sleep before the first poll of a step, in units of 64 clocks
-    uint32_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first offset)
+    uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first four offsets)
     uint64_t *xent;                   // [2][n_tiles][tile_max] further spike ids (tag32 | id)
     uint32_t *abort;                  // set when a wait gives up
     uint64_t *trace;                  // optional [trace_steps][n_tiles][8] phase timestamps
