@@ -324,6 +324,10 @@ constexpr uint32_t kSpinLimit = 1u << 24;    // polls before a wait gives up
 
 // Exclusive prefix sum of one value per thread, in thread order; returns the
 // exclusive prefix and writes the block total to *total.  s_wave: >= 17 ints.
+// Up to 8 waves, one barrier: every wave adds up the totals of the waves before
+// it itself.  More waves: thread 0 turns the wave totals into offsets (two more
+// barriers, fewer LDS reads).  The caller must pass a barrier before the next
+// call reuses s_wave.
 __device__ __forceinline__ int block_scan_excl(int v, int *s_wave, int *total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
@@ -335,6 +339,16 @@ __device__ __forceinline__ int block_scan_excl(int v, int *s_wave, int *total)
     }
     if (lane == 63) s_wave[wave] = incl;
     __syncthreads();
+    if (nwaves <= 8) {
+        int before = 0, all = 0;
+        for (int q = 0; q < nwaves; ++q) {
+            const int x = s_wave[q];
+            before += q < wave ? x : 0;
+            all += x;
+        }
+        *total = all;
+        return before + incl - v;
+    }
     if (threadIdx.x == 0) {
         int run = 0;
         for (int q = 0; q < nwaves; ++q) {
@@ -345,10 +359,8 @@ __device__ __forceinline__ int block_scan_excl(int v, int *s_wave, int *total)
         s_wave[16] = run;
     }
     __syncthreads();
-    const int excl = s_wave[wave] + incl - v;
     *total = s_wave[16];
-    __syncthreads();
-    return excl;
+    return s_wave[wave] + incl - v;
 }
 
 // In-place exclusive scan of a[0..count) in LDS; a[count] receives the total.
