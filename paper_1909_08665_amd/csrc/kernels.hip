@@ -708,18 +708,38 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         // ---- 4. every tile's word of this step: counts and first ids --------------
         if (l < T)
             for (int z = 0; z < P.poll_delay; ++z) __builtin_amdgcn_s_sleep(1);
-        for (int q = l; q < T; q += nthr) {
-            uint64_t w = 0;
-            if (!wait_word(words + q, P.abort, ctl, [tag2](uint64_t x) { return (x >> 62) == tag2; }, w)) {
-                s_abort = 1;
-                break;
+        if (T <= nthr) {
+            // one word per thread: scan the counts straight from the registers
+            int c = 0;
+            if (l < T) {
+                uint64_t w = 0;
+                if (wait_word(words + l, P.abort, ctl, [tag2](uint64_t x) { return (x >> 62) == tag2; }, w)) {
+                    c = static_cast<int>((w >> 48) & 0x3FFFu);
+                    s_word[l] = w;
+                } else {
+                    s_abort = 1;
+                }
             }
-            s_cnt[q] = static_cast<int>((w >> 48) & 0x3FFFu);
-            s_word[q] = w;
+            int total;
+            const int ex = block_scan_excl(c, s_wave, &total);
+            if (l < T) s_cnt[l] = ex;
+            if (l == 0) s_cnt[T] = total;
+            __syncthreads();
+            if (s_abort) break;
+        } else {
+            for (int q = l; q < T; q += nthr) {
+                uint64_t w = 0;
+                if (!wait_word(words + q, P.abort, ctl, [tag2](uint64_t x) { return (x >> 62) == tag2; }, w)) {
+                    s_abort = 1;
+                    break;
+                }
+                s_cnt[q] = static_cast<int>((w >> 48) & 0x3FFFu);
+                s_word[q] = w;
+            }
+            __syncthreads();
+            if (s_abort) break;
+            lds_scan_excl(s_cnt, T, s_wave);
         }
-        __syncthreads();
-        if (s_abort) break;
-        lds_scan_excl(s_cnt, T, s_wave);
         const int S = s_cnt[T];
         if (tr) {
             tr[4] = __builtin_amdgcn_s_memrealtime();
@@ -756,7 +776,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         // ---- 5. delivery into this tile's ring ----------------------------------
         for (int b0 = 0; b0 < S; b0 += kSpkBatch) {
             const int nb = min(kSpkBatch, S - b0);
-            for (int q = l; q < nb; q += nthr) {
+            // spike b0 + q of the step: its id (from its tile's word, or an entry
+            // word from the fifth spike of a tile on) and this tile's sub-row of it
+            auto subrow_of = [&](int q) {
                 const int g = b0 + q;
                 const int src = find_segment(s_cnt, T + 1, g);
                 const int k = g - s_cnt[src];
@@ -770,14 +792,33 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                     }
                     pre = static_cast<int>(static_cast<uint32_t>(w));
                 }
-                const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T];
-                s_beg[q] = static_cast<int>(sr.x);
-                s_pre[q] = static_cast<int>(sr.y);
+                return P.subrow[td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T];
+            };
+            if (nb <= nthr) {
+                // one spike per thread: scan the sub-row lengths from the registers
+                int len = 0;
+                if (l < nb) {
+                    const uint2 sr = subrow_of(l);
+                    s_beg[l] = static_cast<int>(sr.x);
+                    len = static_cast<int>(sr.y);
+                }
+                int total;
+                const int ex = block_scan_excl(len, s_wave, &total);
+                if (l < nb) s_pre[l] = ex;
+                if (l == 0) s_pre[nb] = total;
+                __syncthreads();
+                if (s_abort) break;
+            } else {
+                for (int q = l; q < nb; q += nthr) {
+                    const uint2 sr = subrow_of(q);
+                    s_beg[q] = static_cast<int>(sr.x);
+                    s_pre[q] = static_cast<int>(sr.y);
+                }
+                __syncthreads();
+                if (s_abort) break;
+                lds_scan_excl(s_pre, nb, s_wave);
             }
-            __syncthreads();
-            if (s_abort) break;
             if (tr && b0 == 0) tr[5] = __builtin_amdgcn_s_memrealtime();
-            lds_scan_excl(s_pre, nb, s_wave);
             const int E = s_pre[nb];
             ev_acc += static_cast<unsigned long long>(E);
             deliver_events<SF, kDeliverU>(
