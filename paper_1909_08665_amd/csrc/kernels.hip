@@ -511,6 +511,8 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     extern __shared__ int lds[];
     __shared__ uint64_t s_thr[8 * kPoisMaxDev];
     __shared__ int s_wave[17];
+    __shared__ int s_wave2[17];                        // the wait's scan: waves may still read s_wave
+    __shared__ uint64_t s_mask[16];                    // spike mask of each wave (one neuron per thread)
     __shared__ int s_abort;
     __shared__ long long s_recbase;
 
@@ -676,8 +678,24 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             }
         }
         // ---- 2. compaction and publication ---------------------------------------
+        // One neuron per thread: each wave leaves its spike mask beside its count,
+        // so thread 0 finds the first spikes right after the scan's barrier and
+        // publishes the word without waiting for the compacted list.
+        if (NPT == 1) {
+            const uint64_t m = __ballot(spike[0]);
+            if ((l & 63) == 0) s_mask[l >> 6] = m;
+        }
         int nspk;
         int pos = block_scan_excl(nmine, s_wave, &nspk);
+        if (NPT == 1 && l == 0) {
+            uint64_t w = (tag2 << 62) | (static_cast<uint64_t>(nspk) << 48);
+            const int nw = min(nspk, kWordIds);
+            for (int q = 0, got = 0; got < nw; ++q) {
+                for (uint64_t m = s_mask[q]; m && got < nw; m &= m - 1, ++got)
+                    w |= static_cast<uint64_t>(q * 64 + __builtin_ctzll(m)) << (36 - 12 * got);
+            }
+            store_word(words + tl, w);
+        }
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             if (spike[k]) {
@@ -688,12 +706,14 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 ++pos;
             }
         }
-        __syncthreads();
-        if (l == 0) {
-            uint64_t w = (tag2 << 62) | (static_cast<uint64_t>(nspk) << 48);
-            for (int k = 0; k < min(nspk, kWordIds); ++k)
-                w |= static_cast<uint64_t>(s_own[k] - t0) << (36 - 12 * k);
-            store_word(words + tl, w);
+        if (NPT != 1) {
+            __syncthreads();
+            if (l == 0) {
+                uint64_t w = (tag2 << 62) | (static_cast<uint64_t>(nspk) << 48);
+                for (int k = 0; k < min(nspk, kWordIds); ++k)
+                    w |= static_cast<uint64_t>(s_own[k] - t0) << (36 - 12 * k);
+                store_word(words + tl, w);
+            }
         }
         if (tr) tr[1] = __builtin_amdgcn_s_memrealtime();
         // ---- 3. background input: blocks of step n + 2 into the buffer whose
@@ -721,7 +741,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 }
             }
             int total;
-            const int ex = block_scan_excl(c, s_wave, &total);
+            const int ex = block_scan_excl(c, s_wave2, &total);
             if (l < T) s_cnt[l] = ex;
             if (l == 0) s_cnt[T] = total;
             __syncthreads();
@@ -738,7 +758,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             }
             __syncthreads();
             if (s_abort) break;
-            lds_scan_excl(s_cnt, T, s_wave);
+            lds_scan_excl(s_cnt, T, s_wave2);
         }
         const int S = s_cnt[T];
         if (tr) {
