@@ -316,6 +316,7 @@ namespace mc {
 namespace {
 
 constexpr int kSpkBatch = 2048;              // spikes processed per delivery batch
+constexpr int kSrcDirect = 16;               // most spikes of a tile mapped to their place one by one
 constexpr int kWordIds = 4;                  // spike offsets carried by a tile's word
 constexpr int kDeliverU = 4;                 // records in flight per thread in the step kernel's delivery
 constexpr int kInjectU = 8;                  // and in the injection kernel
@@ -514,6 +515,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     __shared__ int s_wave2[17];                        // the wait's scan: waves may still read s_wave
     __shared__ uint64_t s_mask[16];                    // spike mask of each wave (one neuron per thread)
     __shared__ int s_abort;
+    __shared__ int s_big;                              // step in which some tile sent over kSrcDirect spikes
     __shared__ long long s_recbase;
 
     const DevNet &B = P.base;
@@ -543,6 +545,10 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     int *s_beg = s_cnt + P.max_intiles + 1;            // [kSpkBatch] sub-row start
     int *s_pre = s_beg + kSpkBatch;                    // [kSpkBatch + 1] sub-row lengths -> offsets
     int *s_own = s_pre + kSpkBatch + 1;                // [tmax] this tile's spikes
+    // Between the wait and the ids phase s_beg[g] holds (tile << 16 | index in
+    // it) of spike g of the first batch; each thread reads the entries it then
+    // overwrites with sub-row starts.
+    int *s_src = s_beg;
 
     for (int q = l; q < 8 * kPoisMaxDev; q += nthr) s_thr[q] = B.pois_thr[q];
     for (int s = 0; s < R; ++s) {
@@ -554,7 +560,10 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         }
     }
     for (int q = l; q < W * tmax; q += nthr) ring[q] = 0;
-    if (l == 0) s_abort = 0;
+    if (l == 0) {
+        s_abort = 0;
+        s_big = -1;
+    }
 
     // The tile lies in one instance: its seed and local numbering are uniform.
     const uint64_t seed = B.seeds[B.meta[t0] >> 3];
@@ -742,7 +751,18 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             }
             int total;
             const int ex = block_scan_excl(c, s_wave2, &total);
-            if (l < T) s_cnt[l] = ex;
+            if (l < T) {
+                s_cnt[l] = ex;
+                // spike ex + k of the step is spike k of tile l (the first batch; a
+                // tile with more spikes sends the step to the binary search instead).
+                // Tiles of one neuron per thread only: the instance has many tiles.
+                if (NPT > 1) {
+                } else if (c <= kSrcDirect) {
+                    for (int k = 0; k < c && ex + k < kSpkBatch; ++k) s_src[ex + k] = (l << 16) | k;
+                } else {
+                    s_big = static_cast<int>(n);
+                }
+            }
             if (l == 0) s_cnt[T] = total;
             __syncthreads();
             if (s_abort) break;
@@ -798,10 +818,18 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             const int nb = min(kSpkBatch, S - b0);
             // spike b0 + q of the step: its id (from its tile's word, or an entry
             // word from the fifth spike of a tile on) and this tile's sub-row of it
+            const bool direct = NPT == 1 && b0 == 0 && T <= nthr && s_big != static_cast<int>(n);
             auto subrow_of = [&](int q) {
                 const int g = b0 + q;
-                const int src = find_segment(s_cnt, T + 1, g);
-                const int k = g - s_cnt[src];
+                int src, k;
+                if (direct) {
+                    const int v = s_src[g];
+                    src = v >> 16;
+                    k = v & 0xFFFF;
+                } else {
+                    src = find_segment(s_cnt, T + 1, g);
+                    k = g - s_cnt[src];
+                }
                 int pre = td.inst_n0 + src * td.stride + static_cast<int>((s_word[src] >> (36 - 12 * min(k, 3))) & 0xFFFu);
                 if (k >= kWordIds) {
                     uint64_t w = 0;
