@@ -516,6 +516,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     __shared__ uint64_t s_mask[16];                    // spike mask of each wave (one neuron per thread)
     __shared__ int s_abort;
     __shared__ int s_big;                              // step in which some tile sent over kSrcDirect spikes
+    __shared__ int s_many;                             // step in which some tile sent over kWordIds spikes
     __shared__ long long s_recbase;
 
     const DevNet &B = P.base;
@@ -563,6 +564,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     if (l == 0) {
         s_abort = 0;
         s_big = -1;
+        s_many = -1;
     }
 
     // The tile lies in one instance: its seed and local numbering are uniform.
@@ -737,6 +739,11 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         // ---- 4. every tile's word of this step: counts and first ids --------------
         if (l < T)
             for (int z = 0; z < P.poll_delay; ++z) __builtin_amdgcn_s_sleep(1);
+        // One neuron per thread: the poller of tile l loads the sub-rows of l's
+        // first spikes (ids in l's word) as soon as its wave has every word, and
+        // the loads stay in flight through the count scan and its barriers.
+        uint2 sr[kWordIds];
+        int nk = 0, ex_l = 0;
         if (T <= nthr) {
             // one word per thread: scan the counts straight from the registers
             int c = 0;
@@ -745,12 +752,21 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 if (wait_word(words + l, P.abort, ctl, [tag2](uint64_t x) { return (x >> 62) == tag2; }, w)) {
                     c = static_cast<int>((w >> 48) & 0x3FFFu);
                     s_word[l] = w;
+                    if (NPT == 1) {
+                        nk = min(c, kWordIds);
+                        const int64_t sub_l = td.sub_base + static_cast<int64_t>(l) * td.stride * T;
+#pragma unroll
+                        for (int k = 0; k < kWordIds; ++k)
+                            if (k < nk) sr[k] = P.subrow[sub_l + static_cast<int64_t>((w >> (36 - 12 * k)) & 0xFFFu) * T];
+                    }
                 } else {
                     s_abort = 1;
                 }
             }
             int total;
             const int ex = block_scan_excl(c, s_wave2, &total);
+            ex_l = ex;
+            if (NPT == 1 && c > kWordIds) s_many = static_cast<int>(n);
             if (l < T) {
                 s_cnt[l] = ex;
                 // spike ex + k of the step is spike k of tile l (the first batch; a
@@ -818,6 +834,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             const int nb = min(kSpkBatch, S - b0);
             // spike b0 + q of the step: its id (from its tile's word, or an entry
             // word from the fifth spike of a tile on) and this tile's sub-row of it
+            // every tile at most kWordIds spikes: the sub-rows are in the pollers'
+            // registers (fast); otherwise look them up here
+            const bool fast = NPT == 1 && T <= nthr && S <= kSpkBatch && s_many != static_cast<int>(n);
             const bool direct = NPT == 1 && b0 == 0 && T <= nthr && s_big != static_cast<int>(n);
             auto subrow_of = [&](int q) {
                 const int g = b0 + q;
@@ -842,7 +861,23 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 }
                 return P.subrow[td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T];
             };
-            if (nb <= nthr) {
+            if (fast) {
+                int len = 0;
+#pragma unroll
+                for (int k = 0; k < kWordIds; ++k)
+                    if (k < nk) len += static_cast<int>(sr[k].y);
+                int total;
+                int run = block_scan_excl(len, s_wave, &total);
+#pragma unroll
+                for (int k = 0; k < kWordIds; ++k)
+                    if (k < nk) {
+                        s_beg[ex_l + k] = static_cast<int>(sr[k].x);
+                        s_pre[ex_l + k] = run;
+                        run += static_cast<int>(sr[k].y);
+                    }
+                if (l == 0) s_pre[nb] = total;
+                __syncthreads();
+            } else if (nb <= nthr) {
                 // one spike per thread: scan the sub-row lengths from the registers
                 int len = 0;
                 if (l < nb) {
