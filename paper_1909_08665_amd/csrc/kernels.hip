@@ -317,6 +317,7 @@ namespace {
 
 constexpr int kSpkBatch = 2048;              // spikes processed per delivery batch
 constexpr int kSrcDirect = 16;               // most spikes of a tile mapped to their place one by one
+constexpr int kGroupMin = 8;                 // fewest lanes per spike for delivery by fixed lane groups
 constexpr int kWordIds = 4;                  // spike offsets carried by a tile's word
 constexpr int kDeliverU = 4;                 // records in flight per thread in the step kernel's delivery
 constexpr int kInjectU = 8;                  // and in the injection kernel
@@ -485,6 +486,33 @@ __device__ __forceinline__ void deliver_events(const void *__restrict__ syn, con
         for (int k = 0; k < U; ++k)
             if (e0 + l + k * nthr < E) add(tg[k], d[k], wq[k]);
     }
+}
+
+// Add the events of nb spikes, spike q's sub-row being records s_beg[q] ..
+// s_beg[q] + s_len[q] - 1, with a fixed group of nthr / nb lanes per spike:
+// lane r of spike q's group takes records r, r + group, ... (U in flight), so
+// no scan of the lengths and no search for an event's spike.  Balanced when
+// the sub-rows are about equally long and the groups are wide (the caller
+// ensures nb * 8 <= nthr).  Returns the records this thread added.
+template <int SF, int U, class Add>
+__device__ __forceinline__ unsigned long long deliver_grouped(const void *__restrict__ syn, const int *s_beg,
+                                                              const int *s_len, int nb, Add add)
+{
+    const int l = threadIdx.x, group = static_cast<int>(blockDim.x) / nb;
+    const int q = l / group, r = l - q * group;
+    if (q >= nb) return 0;
+    const uint32_t beg = static_cast<uint32_t>(s_beg[q]);
+    const int len = s_len[q];
+    for (int j0 = r; j0 < len; j0 += U * group) {
+        int wq[U], tg[U], d[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (j0 + k * group < len) wq[k] = syn_record<SF>(syn, beg + static_cast<uint32_t>(j0 + k * group), tg[k], d[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (j0 + k * group < len) add(tg[k], d[k], wq[k]);
+    }
+    return r < len ? static_cast<unsigned long long>((len - r + group - 1) / group) : 0ull;
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b mod 8),
@@ -742,7 +770,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         // One neuron per thread: the poller of tile l loads the sub-rows of l's
         // first spikes (ids in l's word) as soon as its wave has every word, and
         // the loads stay in flight through the count scan and its barriers.
-        uint2 sr[kWordIds];
+        uint2 sr_first[kWordIds];
         int nk = 0, ex_l = 0;
         if (T <= nthr) {
             // one word per thread: scan the counts straight from the registers
@@ -757,7 +785,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                         const int64_t sub_l = td.sub_base + static_cast<int64_t>(l) * td.stride * T;
 #pragma unroll
                         for (int k = 0; k < kWordIds; ++k)
-                            if (k < nk) sr[k] = P.subrow[sub_l + static_cast<int64_t>((w >> (36 - 12 * k)) & 0xFFFu) * T];
+                            if (k < nk) sr_first[k] = P.subrow[sub_l + static_cast<int64_t>((w >> (36 - 12 * k)) & 0xFFFu) * T];
                     }
                 } else {
                     s_abort = 1;
@@ -861,19 +889,30 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 }
                 return P.subrow[td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T];
             };
-            if (fast) {
+            const bool grouped = fast && !BUDGET && nb * kGroupMin <= nthr;
+            if (grouped) {
+                if (l < T) {
+#pragma unroll
+                    for (int k = 0; k < kWordIds; ++k)
+                        if (k < nk) {
+                            s_beg[ex_l + k] = static_cast<int>(sr_first[k].x);
+                            s_pre[ex_l + k] = static_cast<int>(sr_first[k].y);
+                        }
+                }
+                __syncthreads();
+            } else if (fast) {
                 int len = 0;
 #pragma unroll
                 for (int k = 0; k < kWordIds; ++k)
-                    if (k < nk) len += static_cast<int>(sr[k].y);
+                    if (k < nk) len += static_cast<int>(sr_first[k].y);
                 int total;
                 int run = block_scan_excl(len, s_wave, &total);
 #pragma unroll
                 for (int k = 0; k < kWordIds; ++k)
                     if (k < nk) {
-                        s_beg[ex_l + k] = static_cast<int>(sr[k].x);
+                        s_beg[ex_l + k] = static_cast<int>(sr_first[k].x);
                         s_pre[ex_l + k] = run;
-                        run += static_cast<int>(sr[k].y);
+                        run += static_cast<int>(sr_first[k].y);
                     }
                 if (l == 0) s_pre[nb] = total;
                 __syncthreads();
@@ -902,24 +941,27 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 lds_scan_excl(s_pre, nb, s_wave);
             }
             if (tr && b0 == 0) tr[5] = __builtin_amdgcn_s_memrealtime();
-            const int E = s_pre[nb];
-            ev_acc += static_cast<unsigned long long>(E);
-            deliver_events<SF, kDeliverU>(
-                P.syn, s_beg, s_pre, nb, E,
-                [&](int tg, int d, int wq) {
-                    const int ds = static_cast<int>((n + d) & mask);
-                    if (LRING) {
-                        atomicAdd(ring + ds * tmax + tg, wq);
-                    } else if (d <= W) {
-                        int row = wslot + d;
-                        if (row >= W) row -= W;
-                        atomicAdd(ring + row * tmax + tg, wq);
-                    } else {
-                        __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                },
-                t_step, BUDGET ? P.budget_ticks : 0u, &drop_acc);
+            auto add = [&](int tg, int d, int wq) {
+                const int ds = static_cast<int>((n + d) & mask);
+                if (LRING) {
+                    atomicAdd(ring + ds * tmax + tg, wq);
+                } else if (d <= W) {
+                    int row = wslot + d;
+                    if (row >= W) row -= W;
+                    atomicAdd(ring + row * tmax + tg, wq);
+                } else {
+                    __hip_atomic_fetch_add(gring + ds * P.gstride + tg, wq, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            };
+            if (grouped) {
+                ev_acc += deliver_grouped<SF, kDeliverU>(P.syn, s_beg, s_pre, nb, add);
+            } else {
+                const int E = s_pre[nb];
+                if (l == 0) ev_acc += static_cast<unsigned long long>(E);
+                deliver_events<SF, kDeliverU>(P.syn, s_beg, s_pre, nb, E, add, t_step, BUDGET ? P.budget_ticks : 0u,
+                                              &drop_acc);
+            }
             __syncthreads();
         }
         if (s_abort) break;
@@ -956,16 +998,17 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             }
             B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = v;
         }
-    unsigned long long ps = pois_sum, dr = drop_acc;
+    unsigned long long ps = pois_sum, dr = drop_acc, ev = ev_acc;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         ps += __shfl_xor(ps, o, 64);
         dr += __shfl_xor(dr, o, 64);
+        ev += __shfl_xor(ev, o, 64);
     }
+    if ((l & 63) == 0 && ev && !s_abort) atomicAdd(&ctl->events, ev);
     if ((l & 63) == 0 && ps) atomicAdd(&B.pois_acc[t], ps);
     if (BUDGET && (l & 63) == 0 && dr) atomicAdd(&P.dropped[t], dr);
     if (l == 0 && !s_abort) {
-        atomicAdd(&ctl->events, ev_acc);
         if (t == 0) {
             ctl->nbase = n;
             if (T == P.n_tiles) ctl->rec_total = rec_base;
