@@ -860,12 +860,12 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         // ---- 5. delivery into this tile's ring ----------------------------------
         for (int b0 = 0; b0 < S; b0 += kSpkBatch) {
             const int nb = min(kSpkBatch, S - b0);
-            // spike b0 + q of the step: its id (from its tile's word, or an entry
-            // word from the fifth spike of a tile on) and this tile's sub-row of it
             // every tile at most kWordIds spikes: the sub-rows are in the pollers'
             // registers (fast); otherwise look them up here
             const bool fast = NPT == 1 && T <= nthr && S <= kSpkBatch && s_many != static_cast<int>(n);
             const bool direct = NPT == 1 && b0 == 0 && T <= nthr && s_big != static_cast<int>(n);
+            // spike b0 + q of the step: its id (from its tile's word, or an entry
+            // word from the fifth spike of a tile on) and this tile's sub-row of it
             auto subrow_of = [&](int q) {
                 const int g = b0 + q;
                 int src, k;
