@@ -776,6 +776,21 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         if (tr_blk) tr_blk[2] = __builtin_amdgcn_s_memrealtime();
         // ---- 4. every tile's word of this step: counts and first ids --------------
         if (rec_reserve) s_recbase = static_cast<long long>(rec_reserved);
+        // this tile's spikes into its range of the recorder (batch)
+        auto record_reserved = [&]() {
+            for (int q = l; q < nspk; q += nthr) {
+                const int64_t at = s_recbase + q;
+                if (at < B.rec_cap) {
+                    B.rec_id[at] = s_own[q];
+                    B.rec_step[at] = static_cast<int32_t>(n);
+                } else {
+                    atomicOr(&ctl->flags, kFlagRecordOverflow);
+                }
+            }
+        };
+        // a range reserved before the wait is filled even when the wait is
+        // abandoned, so that the recorder never holds unwritten entries
+        const bool reserved_early = NPT > 1 && T != P.n_tiles && nspk > 0;
         if (l < T)
             for (int z = 0; z < P.poll_delay; ++z) __builtin_amdgcn_s_sleep(1);
         // One neuron per thread: the poller of tile l loads the sub-rows of l's
@@ -820,7 +835,10 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             }
             if (l == 0) s_cnt[T] = total;
             __syncthreads();
-            if (s_abort) break;
+            if (s_abort) {
+                if (reserved_early) record_reserved();
+                break;
+            }
         } else {
             for (int q = l; q < T; q += nthr) {
                 uint64_t w = 0;
@@ -832,7 +850,10 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 s_word[q] = w;
             }
             __syncthreads();
-            if (s_abort) break;
+            if (s_abort) {
+                if (reserved_early) record_reserved();
+                break;
+            }
             lds_scan_excl(s_cnt, T, s_wave2);
         }
         const int S = s_cnt[T];
@@ -861,15 +882,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                                                                  static_cast<unsigned long long>(nspk)));
                 __syncthreads();
             }   // else reserved before the wait (s_recbase written before its barrier)
-            for (int q = l; q < nspk; q += nthr) {
-                const int64_t at = s_recbase + q;
-                if (at < B.rec_cap) {
-                    B.rec_id[at] = s_own[q];
-                    B.rec_step[at] = static_cast<int32_t>(n);
-                } else {
-                    atomicOr(&ctl->flags, kFlagRecordOverflow);
-                }
-            }
+            record_reserved();
         }
         // ---- 5. delivery into this tile's ring ----------------------------------
         for (int b0 = 0; b0 < S; b0 += kSpkBatch) {
