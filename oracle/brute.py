@@ -181,3 +181,16 @@ class BruteNet:
                         s = (n + d_) % self.R
                         self.ring[s][b_] += w64 if self.fp64 else wq
             self.step += 1
+
+    def inject(self, ids):
+        """Deliver the rows of the listed neurons as if they had spiked in the
+        step before the current one: weight into slot (step - 1 + delay)."""
+        n = self.step - 1
+        for i in ids:
+            i = int(i)
+            if not 0 <= i < self.N:
+                raise ValueError("neuron id out of range")
+            for (a_, b_, wq, w64, d_) in self.syn:
+                if a_ == i:
+                    s = (n + d_) % self.R
+                    self.ring[s][b_] += w64 if self.fp64 else wq

@@ -64,17 +64,3 @@ def population_stats(steps, ids, pop_offsets, t_start_step, t_end_step, dt_ms=0.
         out[name] = {"rate_hz": float(rate), "cv_isi": float(np.mean(cvs)) if cvs else float("nan"),
                      "corr": corr, "n_cv": len(cvs)}
     return out
-
-
-def freedman_diaconis_edges(x):
-    """Histogram bin edges by the Freedman-Diaconis rule (width 2 IQR n^(-1/3))."""
-    x = np.asarray(x, dtype=np.float64)
-    x = x[np.isfinite(x)]
-    if len(x) < 2:
-        return np.array([0.0, 1.0])
-    q75, q25 = np.percentile(x, [75, 25])
-    w = 2.0 * (q75 - q25) * len(x) ** (-1.0 / 3.0)
-    if w <= 0:
-        return np.array([x.min(), x.max() + 1e-12])
-    nb = int(np.ceil((x.max() - x.min()) / w))
-    return np.linspace(x.min(), x.min() + nb * w, nb + 1)

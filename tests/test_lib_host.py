@@ -69,6 +69,16 @@ def test_missing_table_and_bad_args_rejected():
     L.mc_free(None)
 
 
+def test_overflow_bound_refused_before_upload(conn_table):
+    """Absurd weights: the host builder refuses the network with
+    MC_ERR_OVERFLOW_BOUND (int32 input buffers) before any device memory is
+    touched, as the oracle does for the same parameters."""
+    with pytest.raises(mc.MCError) as e:
+        mc.Network.build(1, 0.1, conn_table, w_mean_pa=1.5e4, w_sd_pa=10.0)
+    assert e.value.code == -4
+    assert b"overflow" in mc.lib().mc_last_error()
+
+
 def _no_gpu():
     try:
         import torch

@@ -3,7 +3,7 @@ Poisson CDF, exact decimal arithmetic, closed-form solutions of Eq. 1
 (Rhodes et al., arXiv 1909.08665, Sec. 2a), the defining property of the
 fixed-total-number connection rule, distribution moments and invariants."""
 import math
-from decimal import Decimal, getcontext
+from decimal import ROUND_FLOOR, Decimal, getcontext
 
 import numpy as np
 import pytest
@@ -210,6 +210,64 @@ def test_population_sizes_2pct(net2):
     assert net2.N == 1544
 
 
+def test_population_sizes_10pct(conn_table):
+    """floor(N * 0.1 + 0.5): the ties 2191.5, 106.5 and 1439.5 round up."""
+    net = O.OracleNet.build(3, 0.1, conn_table.reshape(64))
+    assert np.diff(net.pop_offsets).tolist() == [2068, 583, 2192, 548, 485, 107, 1440, 295]
+    assert net.N == 7718
+
+
+def _k_exact(p, na, nb):
+    """K = ln(1-p) / ln(1 - 1/(Na Nb)) in 60-digit decimal arithmetic, rounded to
+    the nearest integer (halves up): independent of the oracle's double log1p."""
+    if p == 0.0:
+        return 0
+    getcontext().prec = 60
+    num = (Decimal(1) - Decimal(float(p))).ln()
+    den = (Decimal(1) - Decimal(1) / (Decimal(int(na)) * Decimal(int(nb)))).ln()
+    return int((num / den + Decimal("0.5")).to_integral_value(rounding=ROUND_FLOOR))
+
+
+def _pair_counts(net):
+    """Synapses per ordered population pair (pre a, post b), from the CSR."""
+    import ctypes as C
+    rp = np.zeros(net.N + 1, dtype=np.int64)
+    post = np.zeros(net.M, dtype=np.int32)
+    O.lib().or_get_csr(net._h, rp.ctypes.data_as(C.c_void_p), post.ctypes.data_as(C.c_void_p), None, None, None)
+    off = net.pop_offsets
+    pop_of = np.repeat(np.arange(8), np.diff(off))
+    k = np.zeros((8, 8), dtype=np.int64)
+    for a in range(8):
+        seg = post[rp[off[a]]:rp[off[a + 1]]]
+        k[a] = np.bincount(pop_of[seg], minlength=8)
+    return k
+
+
+@pytest.mark.parametrize("scale", [0.02, 0.1, 1.0])
+def test_synapse_count_per_pair_exact(conn_table, scale):
+    """Each ordered pair (a, b) holds exactly K_ab = round(ln(1-p)/ln(1-1/(N_a N_b)))
+    synapses (Sec. 2a: connections by probability; the fixed-total-number reading)."""
+    net = O.OracleNet.build(1, scale, conn_table.reshape(64))
+    sizes = np.diff(net.pop_offsets)
+    got = _pair_counts(net)
+    for a in range(8):
+        for b in range(8):
+            assert got[a, b] == _k_exact(conn_table[a, b], sizes[a], sizes[b]), (scale, a, b)
+    assert net.M == got.sum()
+
+
+def test_synapse_count_log1p_not_log():
+    """N_a = N_b = 20683, p = 0.1: K = 45,071,805.02 -> 45,071,805 (a naive log of
+    1 - 1/N^2 in double gives 45,071,804.37 -> 45,071,804)."""
+    assert _k_exact(0.1, 20683, 20683) == 45071805
+    conn = np.zeros(64)
+    conn[0] = 0.1
+    net = O.OracleNet.build(1, 1.0, conn)
+    assert net.M == 45071805
+    naive = math.log(1 - 0.1) / math.log(1 - 1 / (20683.0 * 20683.0))
+    assert math.floor(naive + 0.5) == 45071804
+
+
 def test_connection_rule_defining_property(net2, conn_table):
     """K uniform draws with replacement leave a fraction p of distinct pairs connected."""
     _, pre, post = _pairs(net2)
@@ -377,3 +435,56 @@ def test_brute_force_dc_input_equals_oracle():
     bf.run(400)
     st, ids = orc.spikes()
     assert list(zip(st.tolist(), ids.tolist())) == bf.spikes and len(bf.spikes) > 10
+
+
+def test_brute_force_injection_equals_oracle():
+    """External stimulation: the rows of listed neurons land in the slots of
+    step (n - 1) + delay, as if they had spiked in the last step (Sec. 3a(ii))."""
+    sizes, pre, post, w, d = _tiny_net(41)
+    for mode in (O.MIRROR, O.FP64):
+        p = O.default_params(mode=mode)
+        orc = O.OracleNet.build_explicit(sizes, pre, post, w, d, params=p, seed=3)
+        bf = brute.BruteNet(sizes, pre, post, w, d, seed=3, fp64=(mode == O.FP64))
+        for k, ids in enumerate(([0, 3, 3, 7], [1, 2, 4, 5, 6, 14], [9])):
+            orc.inject(ids)
+            bf.inject(ids)
+            orc.run(40 + 13 * k)
+            bf.run(40 + 13 * k)
+        st, ids_ = orc.spikes()
+        assert list(zip(st.tolist(), ids_.tolist())) == bf.spikes and len(bf.spikes) > 5
+        u, I, r = orc.state()
+        assert np.array_equal(u, np.array(bf.u, dtype=np.float64))
+        assert np.array_equal(I, np.array(bf.I, dtype=np.float64))
+    with pytest.raises(RuntimeError):
+        orc.inject([sum(sizes)])
+
+
+def test_overflow_bound_exact_edge():
+    """int32 input buffers: the build is refused when some neuron's incoming
+    sum of |weight| (1/256 pA) plus the largest background contribution
+    (24 x 22477) reaches 2^31, and accepted one unit below."""
+    pk = 24 * 22477
+    total = 2 ** 31 - pk                              # 2146944200 = 100 * 21469442
+    assert total == 100 * 21469442
+    sizes = [1, 0, 0, 0, 0, 0, 0, 0]
+    pre = post = [0] * 100
+    d = [1] * 100
+    w_at = [21469442 / 256.0] * 100                   # exact in double
+    with pytest.raises(RuntimeError, match="overflow bound"):
+        O.OracleNet.build_explicit(sizes, pre, post, w_at, d)
+    w_below = [21469442 / 256.0] * 99 + [21469441 / 256.0]
+    net = O.OracleNet.build_explicit(sizes, pre, post, w_below, d)
+    assert net.M == 100
+    # the background term counts: without it the first network would fit
+    p = O.default_params(w_ext_pa=0.0)
+    assert O.OracleNet.build_explicit(sizes, pre, post, w_at, d, params=p).M == 100
+
+
+def test_overflow_bound_microcircuit(conn_table):
+    """Absurd weights in the microcircuit builder: refused by the oracle (and,
+    in test_lib_host, by the library with MC_ERR_OVERFLOW_BOUND)."""
+    p = O.default_params(w_mean_pa=1.5e4, w_sd_pa=10.0)
+    with pytest.raises(RuntimeError, match="overflow bound"):
+        O.OracleNet.build(1, 0.1, conn_table.reshape(64), p)
+    # a tenth of that weight fits
+    assert O.OracleNet.build(1, 0.1, conn_table.reshape(64), O.default_params(w_mean_pa=1.5e3)).M > 0
