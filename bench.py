@@ -25,15 +25,17 @@ DT_S = 1e-4
 HBM_PEAK_GBS = 8000.0
 METRIC = "real-time factor + synaptic events/s, full 77k-neuron microcircuit, 1 GPU"
 WFMT = {"fp32": 0, "fp16": 1, "bf16": 2}
+INIT_MODES = {"uniform": 0, "zero": 1}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None):
+def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None, single_steps=0):
     """The oracle (FP32 mirror) on this host's cores, on a bounded sample of the
-    same workload: same network, `steps` steps after `warm` untimed steps."""
+    same workload: same network, `steps` steps after `warm` untimed steps on
+    every core, then (single_steps > 0) the next single_steps on one thread."""
     from oracle import oracle as O
 
     cores = O.max_threads()
@@ -43,17 +45,29 @@ def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None):
     log(f"oracle build {time.time() - t:.1f}s ({cores} threads)")
     net.run(warm)
     net.spikes(clear=True)
-    c0 = net.counters()
-    t0 = time.perf_counter()
-    net.run(steps)
-    wall = time.perf_counter() - t0
-    c1 = net.counters()
-    ev = c1["events"] - c0["events"]
-    log(f"oracle {steps} steps in {wall:.2f}s")
-    return {"value": round(steps * DT_S / wall, 6), "unit": "x real time (simulated s per wall s)",
-            "events_per_s": round(ev / wall, 1), "cores": cores, "kind": "oracle",
-            "sample": f"FP32-mirror oracle, same seeded network (scale {scale}), steps {warm}..{warm + steps} "
-                      f"({steps * DT_S:.2f} s biological time), build excluded"}
+
+    def timed(n):
+        c0 = net.counters()
+        t0 = time.perf_counter()
+        net.run(n)
+        wall = time.perf_counter() - t0
+        net.spikes(clear=True)
+        return wall, net.counters()["events"] - c0["events"]
+
+    wall, ev = timed(steps)
+    log(f"oracle {steps} steps in {wall:.2f}s on {cores} threads")
+    out = {"value": round(steps * DT_S / wall, 6), "unit": "x real time (simulated s per wall s)",
+           "events_per_s": round(ev / wall, 1), "cores": cores, "kind": "oracle",
+           "sample": f"FP32-mirror oracle, same seeded network (scale {scale}), steps {warm}..{warm + steps} "
+                     f"({steps * DT_S:.2f} s biological time) on {cores} threads, build excluded"}
+    if single_steps:
+        O.set_threads(1)
+        wall1, ev1 = timed(single_steps)
+        O.set_threads(cores)
+        log(f"oracle {single_steps} steps in {wall1:.2f}s on 1 thread")
+        out["single_thread"] = {"value": round(single_steps * DT_S / wall1, 6), "events_per_s": round(ev1 / wall1, 1),
+                                "steps": [warm + steps, warm + steps + single_steps]}
+    return out
 
 
 PHASES = (("update+publish", 0, 1), ("wait for all tiles", 3, 4),
@@ -138,25 +152,29 @@ def delivery_microbench(net, info, args, conn_desc):
             "rows": rows}
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_tiled_full_scale_fp32.md")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_08665_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic_per_step():
-    """HBM bytes per step of k_tiled on the full-scale FP32 workload from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE record, each counter scaled by
-    what it reads for a copy of known size; None when the record is missing or
-    was taken on a different kernel source than the one built here."""
+def measured_traffic_per_launch(workload_key):
+    """HBM bytes per timed launch of the dominant kernel, from a committed
+    rocprofv3 record (FETCH_SIZE and WRITE_SIZE of the timed dispatches, each
+    scaled by what the counter reads for a plain copy of known size) taken on
+    exactly this workload, step count and warm-up, and on the kernel source
+    built here; None when no such record exists."""
+    import glob
     import hashlib
-    try:
-        line = next(l for l in open(PROFILE) if l.startswith("traffic-record:"))
-    except (OSError, StopIteration):
-        return None
-    f = dict(x.strip().rsplit(" ", 1) for x in line.split(":", 1)[1].split(";"))
-    if f.get("kernels.hip sha256") != hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest():
-        return None
-    total = float(f["fetch KiB"]) * float(f["fetch factor"]) + float(f["write KiB"]) * float(f["write factor"])
-    return total * 1024 / float(f["steps per launch"])
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record:"):
+                continue
+            f = dict(x.strip().rsplit(" ", 1) for x in line.split(":", 1)[1].split(";"))
+            if f.get("kernels.hip sha256") != sha or f.get("workload") != workload_key:
+                continue
+            total = float(f["fetch KiB"]) * float(f["fetch factor"]) + float(f["write KiB"]) * float(f["write factor"])
+            return total * 1024 / float(f["launches"])
+    return None
 
 
 def stability_run(args, mc, conn):
@@ -234,6 +252,8 @@ def main():
     ap.add_argument("--engine", choices=["auto", "graph", "tiled"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--init", choices=sorted(INIT_MODES), default="uniform",
+                    help="initial membrane potentials: uniform in [0, theta) (default) or all at rest")
     ap.add_argument("--device-build", action="store_true", help="draw and sort the synapse store on the GPU")
     ap.add_argument("--dc", action="store_true",
                     help="DC-input workload: no Poisson background, each population driven by the mean "
@@ -245,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-warm", type=int, default=1000)
     ap.add_argument("--cpu-steps", type=int, default=5000)
+    ap.add_argument("--cpu-single-steps", type=int, default=300,
+                    help="oracle steps timed on one thread after the multi-thread sample (0: none)")
     ap.add_argument("--d1", action="store_true",
                     help="delivery microbenchmark: inject forced spike lists of 25..77169 neurons")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -289,6 +311,7 @@ def main():
     t = time.time()
     db = int(args.device_build)
     drive = dict(poisson_on=False, i_dc=dc_standin_amplitudes()) if args.dc else {}
+    drive["init_mode"] = INIT_MODES[args.init]
     if n_inst == 1:
         net = mc.Network.build(seeds[0], scales[0], conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db, **drive)
     else:
@@ -337,34 +360,61 @@ def main():
     log(f"{args.steps} steps in {wall:.3f}s: RTF {rtf:.2f}, {events / wall:.3e} events/s, "
         f"{spikes / args.steps:.1f} spikes/step")
 
-    # Roofline of the dominant kernel: algorithmic HBM bytes it must move
-    # (the synapse record of every delivered event, plus per spike the sub-row
-    # descriptors: one 8-byte (start, count) per tile of the spiking neuron's
-    # instance for the tiled engine, one row-pointer pair for the graph engine,
-    # plus the per-neuron state traffic of the graph engine's HBM-resident
-    # state) over its HIP-event-timed duration.
+    # Roofline of the dominant kernel: the algorithmic HBM bytes of the path
+    # per unit of work -- per recurrent event the synapse's target, weight and
+    # delay (4 + 4 + 1 B, or 4 + 2 + 1 B with a 16-bit weight), per spike its
+    # 8-byte row pointer plus, in the tiled form, (T + 1) 4-byte sub-row
+    # pointers of its instance's T tiles, and per neuron-step the state
+    # traffic of the forms that keep it in HBM (graph: 26 B; tiled with the
+    # ring in global memory: 8 B, the slot read and clear) -- times the units
+    # one launch processes, over its HIP-event-timed duration.  The bytes of
+    # the store as actually laid out (packed records of syn_bytes, 8-byte
+    # sub-row entries) are reported beside them.
     tiled = info["engine"] == mc.ENGINE_TILED
-    b_event = info["syn_bytes"]
+    b_event = 9 if args.wfmt == "fp32" else 7
+    tiles_per_inst = info["n_tiles"] / n_inst if tiled else 0
     if tiled:
-        per_spike = 8 * info["n_tiles"] / n_inst
-        per_neuron_step = 0 if info["lds_ring"] else 8          # ring slot read + clear in the global slice
+        per_spike = 8 + (tiles_per_inst + 1) * 4
+        per_neuron_step = 0 if info["lds_ring"] else 8
+        stored_per_spike = 8 * tiles_per_inst
         kname = "k_tiled (persistent step kernel)"
     else:
-        per_spike = 16
+        per_spike = 8
         per_neuron_step = 26
+        stored_per_spike = 16
         kname = "k_neuron + k_deliver (graph-captured step)"
     algo_bytes = events * b_event + spikes * per_spike + args.steps * n_neurons * per_neuron_step
+    stored_bytes = events * info["syn_bytes"] + spikes * stored_per_spike + args.steps * n_neurons * per_neuron_step
     avg_launch_ms = kernel_ms / max(1, launches)
-    achieved = algo_bytes / max(1, launches) / (avg_launch_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
-    traffic = None
-    if tiled and n_inst == 1 and args.config == "full" and args.wfmt == "fp32" and scales[0] == 1.0 and launches:
-        per_step = measured_traffic_per_step()
-        if per_step is not None:
-            traffic = int(per_step * args.steps / launches)
+    per_launch_s = max(1e-12, avg_launch_ms * 1e-3)
+    achieved = algo_bytes / max(1, launches) / per_launch_s / 1e9 if kernel_ms > 0 else 0.0
+    workload_key = (f"{args.config}/{args.wfmt}/scale={scales[0] if n_inst == 1 else 'batch'}/steps={args.steps}/"
+                    f"warmup={args.warmup}/engine={'tiled' if tiled else 'graph'}/dc={int(args.dc)}/"
+                    f"budget={args.step_budget:g}/init={args.init}")
+    traffic = measured_traffic_per_launch(workload_key) if launches else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": kname,
+                "frac": round(achieved / HBM_PEAK_GBS, 6),
+                "traffic": int(traffic) if traffic is not None else None, "kernel": kname,
                 "launches": launches, "avg_launch_ms": round(avg_launch_ms, 4),
-                "bytes_per_launch": int(algo_bytes / max(1, launches))}
+                "bytes_per_launch": int(algo_bytes / max(1, launches)),
+                "stored_layout": {"bytes_per_launch": int(stored_bytes / max(1, launches)),
+                                  "achieved": round(stored_bytes / max(1, launches) / per_launch_s / 1e9, 3)
+                                  if kernel_ms > 0 else 0.0},
+                "workload_key": workload_key}
+    # Atomic throughput: every recurrent event is one int32 atomic add into a
+    # ring slot -- LDS atomics when the tile rings sit in LDS, device atomics
+    # otherwise -- against the ceiling the probe measures on this device.
+    atomics = None
+    if kernel_ms > 0:
+        if tiled and info["lds_ring"]:
+            peak, akind = mc.probe(mc.PROBE_LDS_ATOMICS)[0], "LDS int32 atomic add (random words)"
+        else:
+            ring_bytes = info["ring_depth"] * n_neurons * 4
+            peak, akind = mc.probe(mc.PROBE_DEVICE_ATOMICS, max(8192, ring_bytes))[0], \
+                f"device int32 atomic add (random words of a {ring_bytes / 2**20:.0f} MiB buffer)"
+        rate = events / max(1, launches) / per_launch_s
+        atomics = {"achieved": round(rate, 1), "peak": round(peak, 1), "unit": "atomics/s",
+                   "frac": round(rate / peak, 6) if peak else None, "kind": akind}
 
     latency = step_latency(net) if args.trace and tiled else None
 
@@ -400,6 +450,7 @@ def main():
         "max_spikes_per_step": c1["max_spikes_per_step"],
         "context": {"paper_spinnaker_rtf": 1.0, "paper_spinnaker_events_per_s": 9.343e8},
         "roofline": roofline,
+        "atomics": atomics,
     }
     if latency:
         out["step_latency"] = latency
@@ -407,7 +458,7 @@ def main():
     if not args.no_cpu_baseline:
         # one instance of the workload (the first) on the host cores, scaled to the batch
         cb = cpu_baseline(seeds[0], scales[0], conn, args.cpu_warm, args.cpu_steps,
-                          i_dc=dc_standin_amplitudes() if args.dc else None)
+                          i_dc=dc_standin_amplitudes() if args.dc else None, single_steps=args.cpu_single_steps)
         if n_inst > 1:
             cb["sample"] += f"; instance 0 of {n_inst} (per-instance rate)"
         out["cpu_baseline"] = cb

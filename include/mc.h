@@ -153,6 +153,10 @@ typedef struct mc_launch {
     int32_t poll_delay;          /* TILED engine: sleep before a step's first poll of the other
                                     tiles' words, in units of 64 clocks, 1..255; -1 for none.
                                     Speed only: results do not depend on it. */
+    int32_t coop;                /* TILED engine: 1 cooperative launch (the runtime guarantees
+                                    that all workgroups are resident at once; the default),
+                                    2 ordinary launch (relies on the occupancy check made at
+                                    set-up).  Speed only. */
 } mc_launch;
 
 /* Fill *cfg with the defaults of Sec. 2a; conn_probs is left NULL. */
@@ -180,26 +184,45 @@ int mc_build_batch(const uint64_t *seeds, const double *scales, int32_t n,
                    const mc_config *cfg, struct mc_net **out);
 
 /*
- * Advance the network by `steps` steps (synchronous: returns when the GPU is done).
- * mc_run(a); mc_run(b) gives bit-identical results to mc_run(a + b).
- * Errors: MC_ERR_ARG (steps < 0), MC_ERR_HIP, MC_ERR_RECORD_OVERFLOW (the spikes
- * that did not fit are lost; counters still count them).
+ * Advance the network by `steps` steps of dt (Sec. 2a: fixed-step simulation of
+ * Eq. 1 at dt = 0.1 ms).  Each step consumes and clears every neuron's input-
+ * buffer slot for the step, adds the step's Poisson background (Sec. 3a(ii) and
+ * 3a(iii): a count of background spikes per neuron per timer tick), integrates
+ * Eq. 1 exactly, records the spikes, and adds every spiking neuron's synaptic row
+ * into the targets' slots `delay` steps ahead (Sec. 3a(ii)).
+ * Synchronous: returns when the GPU is done.  mc_run(a); mc_run(b) gives
+ * bit-identical results to mc_run(a + b).  The step index (steps already run
+ * plus `steps`) must stay below 2^31, i.e. about 59.6 h of biological time at
+ * dt = 0.1 ms; a longer run is refused with MC_ERR_ARG before anything runs.
+ * Errors: MC_ERR_ARG (steps < 0, step limit), MC_ERR_HIP (a HIP call failed, or a
+ * workgroup's wait for the other tiles' spikes timed out: the network is then
+ * marked failed and every later call on it except mc_load_state, mc_get_info,
+ * mc_instance_size, mc_last_error and mc_free returns MC_ERR_HIP until a checkpoint
+ * is loaded), MC_ERR_RECORD_OVERFLOW (the spikes that did not fit are lost;
+ * counters still count them).
  */
 int mc_run(struct mc_net *net, int64_t steps);
 
 /*
  * Copy out and consume the spikes of `instance` recorded since the previous call,
- * sorted by (step, id).  steps_out/ids_out have room for `cap` entries;
- * *count_out receives the number of spikes.  If cap is too small, returns
- * MC_ERR_BUFFER_TOO_SMALL with *count_out = the number needed and consumes nothing.
+ * sorted by (step, id): the output spike trains from which the paper's results
+ * are computed (Sec. 2a: spike trains after the initial transient; Sec. 4b:
+ * rates, CV of the inter-spike interval, correlations), a spike at step n meaning
+ * V crossed the threshold in that step (Eq. 1).  steps_out/ids_out have room for
+ * `cap` entries; *count_out receives the number of spikes.  If cap is too small,
+ * returns MC_ERR_BUFFER_TOO_SMALL with *count_out = the number needed and consumes
+ * nothing.  Errors: MC_ERR_ARG (NULL pointers, instance out of range).
  */
 int mc_get_spikes(struct mc_net *net, int32_t instance, int64_t *steps_out, int32_t *ids_out,
                   int64_t cap, int64_t *count_out);
 
 /*
- * Copy the state of `instance`: u = V - E_L in mV, synaptic current in pA,
- * remaining refractory steps.  Any output pointer may be NULL.  `n` must equal
- * the instance's neuron count (MC_ERR_ARG otherwise).
+ * Copy the state of `instance`: the two state variables of Eq. 1 (Sec. 2a) --
+ * membrane potential relative to rest, u = V - E_L in mV, and synaptic current
+ * I_syn in pA -- and the remaining refractory steps (V held at V_reset for t_ref
+ * after a spike).  u_mv, i_pa: float [n]; refr: int32 [n]; host memory owned by
+ * the caller; any output pointer may be NULL.  `n` must equal the instance's
+ * neuron count.  Errors: MC_ERR_ARG (n or instance wrong), MC_ERR_HIP.
  */
 int mc_get_state(struct mc_net *net, int32_t instance, float *u_mv, float *i_pa, int32_t *refr, int64_t n);
 
@@ -208,9 +231,13 @@ int mc_set_state(struct mc_net *net, int32_t instance, const float *u_mv, const 
                  const int32_t *refr, int64_t n);
 
 /*
- * Counters of `instance` (spikes, events, largest step) over the spikes
- * recorded so far; instance = -1 gives the whole network.  poisson_events is
- * always the whole-network value.
+ * Counters of `instance` over the spikes recorded so far: steps, spikes,
+ * synaptic events -- one spike reaching one postsynaptic synapse (Sec. 3c),
+ * i.e. the sum of the out-degrees of the spiking neurons, recurrent only --,
+ * background (Poisson) spikes drawn (Sec. 3a(iii)) and the largest spike count
+ * of one step.  instance = -1 gives the whole network; poisson_events is always
+ * the whole-network value.  *out is caller-owned host memory.
+ * Errors: MC_ERR_ARG (NULL pointer, instance out of range), MC_ERR_HIP.
  */
 int mc_get_counters(struct mc_net *net, int32_t instance, mc_counters *out);
 
@@ -295,6 +322,55 @@ int mc_get_trace(struct mc_net *net, uint64_t *out, int64_t cap, int64_t *count)
  */
 int mc_save_state(struct mc_net *net, const char *path);
 int mc_load_state(struct mc_net *net, const char *path);
+
+/*
+ * Delivery-path counters of the TILED engine (which code path delivered each
+ * step's spikes), summed over tiles and steps since the network was built:
+ * counts[k] for k < n (entries beyond the ones defined are 0):
+ *   0 steps without spikes;  1 ids from the tile words, fixed lane groups per
+ *   spike;  2 ids from the tile words, events spread by a length scan;  3 one
+ *   spike per thread, ids looked up;  4 more spikes than threads;  5 spike
+ *   batches after the first (steps of more than 2048 spikes);  6 looked-up ids
+ *   placed by the per-tile map;  7 placed by a binary search;  8 some tile sent
+ *   more spikes than its exchange word carries (ids read from entry words).
+ * Counts are per tile and step (and batch).  For coverage checks; results do
+ * not depend on the path.  Errors: MC_ERR_ARG, MC_ERR_HIP.
+ */
+int mc_get_paths(struct mc_net *net, int64_t *counts, int32_t n);
+
+/*
+ * Bound on a cross-tile wait of the TILED engine: a workgroup that has polled
+ * another tile's spike word `polls` times (checked every 1024 polls) without
+ * seeing it gives up, and so does every other workgroup of the launch; mc_run
+ * then returns MC_ERR_HIP and the network is marked failed (see mc_run).
+ * Default 2^24 polls (seconds of waiting: a wait that long means the launch
+ * cannot complete).  polls = 0 makes every wait give up at once -- for testing
+ * the failure path without a real fault.  Errors: MC_ERR_ARG (polls outside
+ * [0, 2^32 - 1]).
+ */
+int mc_set_wait_limit(struct mc_net *net, int64_t polls);
+
+/*
+ * Ceilings of the memory system the step kernels run against, measured on the
+ * current device (no network needed).  The delivery of Sec. 3a(ii) adds each
+ * event's weight into a ring slot with an integer atomic and streams the
+ * synaptic rows from HBM, so these bound it:
+ *   MC_PROBE_HBM_COPY       streaming copy of `bytes` (half read, half written):
+ *                           *rate in GB/s;
+ *   MC_PROBE_LDS_ATOMICS    int32 atomic adds at random LDS words in every
+ *                           compute unit (the tiled engine's ring): atomics/s;
+ *                           `bytes` ignored;
+ *   MC_PROBE_DEVICE_ATOMICS device-scope int32 atomic adds at random words of a
+ *                           `bytes` buffer (L2-, Infinity-Cache- or HBM-resident
+ *                           by size; the global-ring and graph forms): atomics/s.
+ * *kernel_ms (may be NULL) receives the timed launch's duration.  Allocates and
+ * frees its own device buffers.  Errors: MC_ERR_ARG (unknown kind, bytes outside
+ * [8 KiB, 64 GiB]), MC_ERR_NOMEM, MC_ERR_HIP.
+ */
+#define MC_PROBE_HBM_COPY 0
+#define MC_PROBE_LDS_ATOMICS 1
+#define MC_PROBE_DEVICE_ATOMICS 2
+int mc_probe(int32_t kind, int64_t bytes, double *rate, double *kernel_ms);
 
 /* Release the network and all of its device memory.  NULL is allowed. */
 void mc_free(struct mc_net *net);

@@ -56,7 +56,7 @@ class McInfo(C.Structure):
 
 class McLaunch(C.Structure):
     _fields_ = [("engine", C.c_int32), ("tile", C.c_int32), ("ring", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
-                ("deliver_grid", C.c_int32), ("poll_delay", C.c_int32)]
+                ("deliver_grid", C.c_int32), ("poll_delay", C.c_int32), ("coop", C.c_int32)]
 
 
 # Every entry point declared in include/mc.h.
@@ -64,7 +64,8 @@ EXPORTS = ("mc_config_default", "mc_build_network", "mc_build_batch", "mc_run", 
            "mc_get_state", "mc_set_state", "mc_get_counters", "mc_get_info", "mc_get_csr",
            "mc_instance_size", "mc_set_launch", "mc_tune", "mc_set_stream", "mc_set_timing",
            "mc_get_timing", "mc_set_trace", "mc_get_trace", "mc_save_state", "mc_load_state", "mc_free",
-           "mc_last_error", "mc_inject_spikes", "mc_set_step_budget")
+           "mc_last_error", "mc_inject_spikes", "mc_set_step_budget", "mc_set_wait_limit",
+           "mc_get_paths", "mc_probe")
 
 _lib = None
 
@@ -110,10 +111,24 @@ def lib():
     L.mc_save_state.argtypes = [P, C.c_char_p]
     L.mc_load_state.argtypes = [P, C.c_char_p]
     L.mc_set_step_budget.argtypes = [P, C.c_double]
+    L.mc_set_wait_limit.argtypes = [P, I64]
+    L.mc_get_paths.argtypes = [P, P, I32]
+    L.mc_probe.argtypes = [I32, I64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.mc_free.argtypes = [P]
     L.mc_free.restype = None
     _lib = L
     return L
+
+
+PROBE_HBM_COPY, PROBE_LDS_ATOMICS, PROBE_DEVICE_ATOMICS = 0, 1, 2
+
+
+def probe(kind, nbytes=0):
+    """Memory-system ceiling on the current device: (rate, kernel ms); rate in
+    GB/s for PROBE_HBM_COPY, atomics/s for the atomic probes."""
+    rate, ms = C.c_double(), C.c_double()
+    _check(lib().mc_probe(int(kind), int(nbytes), C.byref(rate), C.byref(ms)))
+    return rate.value, ms.value
 
 
 def _check(rc):
@@ -191,11 +206,13 @@ class Network:
     def run(self, steps):
         _check(lib().mc_run(self._h, int(steps)))
 
-    def set_launch(self, engine=0, tile=0, ring=0, graph_chunk=0, seg=0, block=0, deliver_grid=0, poll_delay=0):
+    def set_launch(self, engine=0, tile=0, ring=0, graph_chunk=0, seg=0, block=0, deliver_grid=0, poll_delay=0,
+                   coop=0):
         """ring: 0 auto, 1 tile ring in LDS, 2 tile ring in global memory (tiled engine).
         poll_delay: tiled engine, sleep before polling in units of 64 clocks (-1 none).
+        coop: tiled engine, 1 cooperative launch, 2 ordinary launch.
         0 keeps the current value of any knob."""
-        l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid, poll_delay)
+        l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid, poll_delay, coop)
         _check(lib().mc_set_launch(self._h, C.byref(l)))
 
     def set_step_budget(self, budget_us):
@@ -203,6 +220,20 @@ class Network:
         within budget_us of the step's start are dropped and counted in
         counters()["dropped_events"]; 0 turns it off."""
         _check(lib().mc_set_step_budget(self._h, float(budget_us)))
+
+    def set_wait_limit(self, polls):
+        """Polls after which a cross-tile wait of the tiled engine gives up
+        (0: at once, to exercise the failure path)."""
+        _check(lib().mc_set_wait_limit(self._h, int(polls)))
+
+    PATHS = ("no_spikes", "grouped", "fast", "per_thread", "batched", "extra_batch", "direct_map", "search",
+             "entry_words")
+
+    def paths(self):
+        """Tile-steps per delivery path of the tiled engine (coverage counters)."""
+        out = np.zeros(len(self.PATHS), dtype=np.int64)
+        _check(lib().mc_get_paths(self._h, _ptr(out), len(out)))
+        return dict(zip(self.PATHS, out.tolist()))
 
     def tune(self, trial_steps=200):
         _check(lib().mc_tune(self._h, int(trial_steps)))

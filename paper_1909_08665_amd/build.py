@@ -31,16 +31,16 @@ def _run(cmd):
 
 
 def build(verbose=False):
+    """Compile every source (in parallel) and link libmc.so."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in ("netbuild.cpp",):
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-    for src in ("kernels.hip", "engine.hip", "devbuild.hip"):
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    jobs = [["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "netbuild.cpp"), "-o", os.path.join(BUILD, "netbuild.cpp.o")]]
+    for src in ("kernels.hip", "engine.hip", "devbuild.hip", "probe.hip"):
+        jobs.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
+    objs = [j[-1] for j in jobs]
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for f in [ex.submit(_run, j) for j in jobs]:
+            f.result()
     tmp = LIB + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp])
     os.replace(tmp, LIB)

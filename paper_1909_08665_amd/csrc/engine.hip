@@ -36,6 +36,13 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+#define LIVE_OR_FAIL(net)                                                                      \
+    do {                                                                                       \
+        if ((net)->failed)                                                                     \
+            return fail(MC_ERR_HIP, "the network failed in an earlier run (" + (net)->fail_msg +   \
+                                        "); load a checkpoint to continue");                   \
+    } while (0)
+
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -44,6 +51,9 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 constexpr int64_t kSegMin = 100, kSegMax = 10000;   // steps between recorder drains
+// Tile words carry (n mod 32767) + 1: words left by earlier launches can be
+// taken for a new launch's only if the step index jumped ahead by about 2^15.
+constexpr int64_t kTagSafe = 32767 - kSegMax - 8;
 // Tiled engine: sleep before a step's first poll, in units of 64 clocks, when
 // the instances have at least kPollDelayTiles tiles (T tiles each polling T
 // words congest the lines the last stores go to); none for fewer tiles.
@@ -77,17 +87,13 @@ struct mc_net {
     uint64_t *work = nullptr;
     unsigned long long *pois_acc = nullptr;
     int64_t pois_slots = 0;
-    int32_t *rec_id = nullptr, *rec_step = nullptr;
+    // Two spike recorders (step << 32 | id) and their pinned host copies: the
+    // tiled engine alternates them between segments and drains one while the
+    // next segment runs; the graph engine uses the first.
+    uint64_t *rec[2] = {};
+    uint64_t *h_rec[2] = {};
     int64_t rec_cap = 0;
-
-    // pinned staging for recorder drains
-    int32_t *h_rec_id = nullptr, *h_rec_step = nullptr;
     mc::StepCtl *h_ctl = nullptr;
-    // Second recorder, pinned copies and counter snapshot: the tiled engine
-    // alternates recorders between segments and drains one while the next runs.
-    int32_t *rec_id1 = nullptr, *rec_step1 = nullptr;
-    int32_t *h_rec_id1 = nullptr, *h_rec_step1 = nullptr;
-    mc::StepCtl *h_ctl1 = nullptr;
     hipStream_t copy_stream = nullptr;
     hipEvent_t seg_ev0[2] = {}, seg_ev1[2] = {}, snap_ev[2] = {};
 
@@ -105,11 +111,20 @@ struct mc_net {
     int32_t syn_fmt = 0;
     uint64_t *xchg = nullptr;
     uint64_t *xent = nullptr;
-    unsigned long long *dropped_acc = nullptr;   // [2][n_tiles], one half per recorder
-    unsigned long long *h_dropped = nullptr;     // pinned copy
+    // Per-launch counters: TiledCtl followed by the dropped-event counts
+    // [2][n_tiles]; copied whole into h_tblk[buf] after each launch.
+    void *tblk = nullptr;
+    void *h_tblk[2] = {};
+    unsigned long long *paths = nullptr;         // [kPaths] tile-steps per delivery path
+    size_t tblk_bytes = 0;
     uint32_t budget_ticks = 0;                   // step budget, 100 MHz ticks; 0: none
     int64_t xent_high = 0;            // entry words may carry tags of steps below this
-    uint32_t *abort_flag = nullptr;
+    int64_t xchg_high = 0;            // tile words carry tags of steps below this
+    bool exch_dirty = true;           // tile words and counters must be cleared before the next launch
+    int next_buf = 0;                 // recorder buffer of the next launch
+    uint32_t epoch = 0;               // launches so far (the abort word names a launch)
+    uint32_t spin_limit = mc::kSpinLimitDefault;
+    double rec_rate = 64.0;           // spikes per step of the last segment (recorder copy size)
     uint64_t *trace = nullptr;
     int32_t trace_steps = 0;
     int32_t trace_tiles = 0;
@@ -125,6 +140,8 @@ struct mc_net {
     int deliver_grid = 1024;
     int poll_delay = 0;
     bool poll_delay_set = false;      // chosen by mc_set_launch or the tuner; otherwise by tile count
+    bool coop = true;                 // tiled engine: cooperative launch
+    int lanes = 16;                   // tiled engine: lanes per spike for cursor delivery
     hipGraphExec_t graph_exec = nullptr;
     int graph_k = 0;
 
@@ -136,6 +153,11 @@ struct mc_net {
     int64_t max_step_spikes = 0;
     int64_t steps_in_flight = 0;      // steps of the segment being drained
     bool overflow = false;
+    // Set when a run failed part-way (a HIP error or an abandoned cross-tile
+    // wait): the state is then inconsistent, and calls that read or advance it
+    // are refused until a checkpoint is loaded.
+    bool failed = false;
+    std::string fail_msg;
 
     // kernel timing
     bool timing = false;
@@ -186,8 +208,7 @@ mc::DevNet dev_view(const mc_net *nt)
     d.ctl = nt->ctl;
     d.work = nt->work;
     d.pois_acc = nt->pois_acc;
-    d.rec_id = nt->rec_id;
-    d.rec_step = nt->rec_step;
+    d.rec = nt->rec[0];
     d.rec_cap = nt->rec_cap;
     return d;
 }
@@ -196,15 +217,17 @@ void release(mc_net *nt)
 {
     if (!nt) return;
     if (nt->graph_exec) hipGraphExecDestroy(nt->graph_exec);
+    // Nothing may still run on the streams when their buffers go.
+    if (nt->stream) hipStreamSynchronize(nt->stream);
+    if (nt->copy_stream) hipStreamSynchronize(nt->copy_stream);
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
-                    nt->rec_id, nt->rec_step, nt->subrow, nt->syn, nt->xchg, nt->xent, nt->abort_flag, nt->trace,
-                    nt->tiles_dev, nt->gring, nt->inject_buf, nt->rec_id1, nt->rec_step1, nt->dropped_acc};
+                    nt->rec[0], nt->rec[1], nt->subrow, nt->syn, nt->xchg, nt->xent, nt->tblk, nt->trace, nt->paths,
+                    nt->tiles_dev, nt->gring, nt->inject_buf};
     for (void *b : bufs)
         if (b) hipFree(b);
-    for (void *b : {static_cast<void *>(nt->h_rec_id), static_cast<void *>(nt->h_rec_step), static_cast<void *>(nt->h_ctl),
-                    static_cast<void *>(nt->h_rec_id1), static_cast<void *>(nt->h_rec_step1),
-                    static_cast<void *>(nt->h_ctl1), static_cast<void *>(nt->h_dropped)})
+    for (void *b : {static_cast<void *>(nt->h_rec[0]), static_cast<void *>(nt->h_rec[1]), static_cast<void *>(nt->h_ctl),
+                    nt->h_tblk[0], nt->h_tblk[1]})
         if (b) hipHostFree(b);
     if (nt->ev0) hipEventDestroy(nt->ev0);
     if (nt->ev1) hipEventDestroy(nt->ev1);
@@ -315,15 +338,11 @@ int upload(mc_net *nt, const mc_config *cfg, const std::vector<mc::SynSeg> *segs
     int64_t cap = cfg->record_capacity;
     if (cap <= 0) cap = std::max<int64_t>(int64_t{1} << 22, 64 * N);
     nt->rec_cap = cap;
-    if ((rc = dalloc(&nt->rec_id, cap)) || (rc = dalloc(&nt->rec_step, cap)) || (rc = dalloc(&nt->rec_id1, cap)) ||
-        (rc = dalloc(&nt->rec_step1, cap)))
-        return rc;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_id), cap * sizeof(int32_t), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_step), cap * sizeof(int32_t), hipHostMallocDefault));
+    for (int b = 0; b < 2; ++b) {
+        if ((rc = dalloc(&nt->rec[b], cap))) return rc;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec[b]), cap * sizeof(uint64_t), hipHostMallocDefault));
+    }
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl), sizeof(mc::StepCtl), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_id1), cap * sizeof(int32_t), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec_step1), cap * sizeof(int32_t), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl1), sizeof(mc::StepCtl), hipHostMallocDefault));
 
     // Static data.
     HIP_TRY(hipMemcpy(nt->meta, H.meta.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -433,29 +452,39 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     if (static_cast<int64_t>(per_cu) * nt->n_cu < T)
         return fail(MC_ERR_UNSUPPORTED, "tiles cannot all be resident at once (" + std::to_string(T) + " tiles)");
     if (nt->tile == target && nt->tiled_shape.lds_ring == sh.lds_ring && nt->subrow) return MC_OK;
+    HIP_TRY(hipStreamSynchronize(nt->stream));
     for (void *b : {static_cast<void *>(nt->subrow), static_cast<void *>(nt->syn), static_cast<void *>(nt->xchg),
-                    static_cast<void *>(nt->xent), static_cast<void *>(nt->abort_flag), static_cast<void *>(nt->tiles_dev),
-                    static_cast<void *>(nt->gring), static_cast<void *>(nt->dropped_acc)})
+                    static_cast<void *>(nt->xent), nt->tblk, static_cast<void *>(nt->tiles_dev),
+                    static_cast<void *>(nt->gring)})
         if (b) hipFree(b);
-    if (nt->h_dropped) hipHostFree(nt->h_dropped);
-    nt->dropped_acc = nullptr;
-    nt->h_dropped = nullptr;
+    for (void *&b : nt->h_tblk) {
+        if (b) hipHostFree(b);
+        b = nullptr;
+    }
+    nt->tblk = nullptr;
     nt->gring = nullptr;
     nt->gstride = 0;
     nt->subrow = nullptr;
     nt->syn = nullptr;
     nt->xchg = nullptr;
     nt->xent = nullptr;
-    nt->abort_flag = nullptr;
     nt->tiles_dev = nullptr;
     nt->tile = 0;
+    nt->exch_dirty = true;
     int rc;
     if ((rc = dalloc(&nt->subrow, static_cast<size_t>(sub_total))) || (rc = dalloc(&nt->xchg, 2 * T)) ||
-        (rc = dalloc(&nt->xent, static_cast<size_t>(2) * T * tile_max)) || (rc = dalloc(&nt->abort_flag, 1)) ||
-        (rc = dalloc(&nt->tiles_dev, T)) || (rc = dalloc(&nt->dropped_acc, 2 * static_cast<size_t>(T))))
+        (rc = dalloc(&nt->xent, static_cast<size_t>(2) * T * tile_max)) || (rc = dalloc(&nt->tiles_dev, T)))
         return rc;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_dropped), 2 * static_cast<size_t>(T) * sizeof(unsigned long long),
-                          hipHostMallocDefault));
+    if (!nt->paths) {
+        if ((rc = dalloc(&nt->paths, mc::kPaths))) return rc;
+        HIP_TRY(hipMemset(nt->paths, 0, mc::kPaths * sizeof(unsigned long long)));
+    }
+    nt->tblk_bytes = sizeof(mc::TiledCtl) + 2 * static_cast<size_t>(T) * sizeof(unsigned long long);
+    {
+        hipError_t e = hipMalloc(&nt->tblk, nt->tblk_bytes);
+        if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    for (void *&b : nt->h_tblk) HIP_TRY(hipHostMalloc(&b, nt->tblk_bytes, hipHostMallocDefault));
     if (!sh.lds_ring) {
         nt->gstride = ((tile_max + 31) / 32) * 32;
         if ((rc = dalloc(&nt->gring, static_cast<size_t>(T) * nt->host.ring * nt->gstride))) return rc;
@@ -483,6 +512,9 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
         if (e != hipSuccess) return fail(MC_ERR_HIP, std::string("tiled store build: ") + hipGetErrorString(e));
     }
     nt->syn_fmt = sf;
+    // lanes per spike for cursor delivery: about the mean sub-row length
+    nt->lanes = static_cast<int>(std::min<int64_t>(
+        64, std::max<int64_t>(4, (nt->host.m + std::max<int64_t>(1, sub_total) - 1) / std::max<int64_t>(1, sub_total))));
     nt->tile = target;
     nt->tiles_host = tiles;
     nt->n_tiles = T;
@@ -575,13 +607,12 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
 }
 
 
-// Fold the spikes of the steps [s0, s0 + span) that a recorder holds (counter
-// snapshot c, host copies ids/steps) into the per-instance record and counters,
-// and check the error flags.
-int absorb(mc_net *nt, const mc::StepCtl &c, const int32_t *rec_ids, const int32_t *rec_steps, int64_t s0,
-           int64_t span)
+// Fold the spikes of the steps [s0, s0 + span) that a recorder holds (`total`
+// recorded, `flags` of the launch, host copy `recs`) into the per-instance
+// record and counters, and check the error flags.
+int absorb(mc_net *nt, int64_t total, uint32_t flags, const uint64_t *recs, int64_t s0, int64_t span)
 {
-    const int64_t total = c.rec_total;
+    if (flags & mc::kFlagTimeout) return fail(MC_ERR_HIP, "a cross-tile wait timed out");
     const int64_t got = std::min(total, nt->rec_cap);
     const auto &rp = nt->host.row_ptr;
     const auto &meta = nt->host.meta;
@@ -611,11 +642,11 @@ int absorb(mc_net *nt, const mc::StepCtl &c, const int32_t *rec_ids, const int32
         int64_t q0, q1;
         chunk(t, q0, q1);
         for (int64_t q = q0; q < q1; ++q) {
-            const int32_t gid = rec_ids[q];
+            const int32_t gid = static_cast<int32_t>(static_cast<uint32_t>(recs[q]));
             const int inst = static_cast<int>(meta[gid] >> 3);
             P.cnt[inst] += 1;
             P.ev[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
-            const int64_t k = rec_steps[q] - s0;
+            const int64_t k = static_cast<int64_t>(recs[q] >> 32) - s0;
             if (k >= 0 && k < span) {
                 P.per_step[k] += 1;
                 if (n_inst > 1) P.per_inst_step[static_cast<size_t>(k) * n_inst + inst] += 1;
@@ -628,9 +659,10 @@ int absorb(mc_net *nt, const mc::StepCtl &c, const int32_t *rec_ids, const int32
         int64_t q0, q1;
         chunk(t, q0, q1);
         for (int64_t q = q0; q < q1; ++q) {
-            const int32_t gid = rec_ids[q];
+            const int32_t gid = static_cast<int32_t>(static_cast<uint32_t>(recs[q]));
             const int inst = static_cast<int>(meta[gid] >> 3);
-            nt->unread[inst][static_cast<size_t>(cur[inst]++)] = {rec_steps[q], gid - nt->host.inst_off[inst]};
+            nt->unread[inst][static_cast<size_t>(cur[inst]++)] = {static_cast<int64_t>(recs[q] >> 32),
+                                                                  gid - nt->host.inst_off[inst]};
         }
     };
     auto parallel = [nth](auto &&f) {
@@ -667,8 +699,7 @@ int absorb(mc_net *nt, const mc::StepCtl &c, const int32_t *rec_ids, const int32
             for (int j = 0; j < nt->host.n_inst; ++j)
                 nt->inst_max_step[j] = std::max<int64_t>(nt->inst_max_step[j], per_inst_step[static_cast<size_t>(k) * nt->host.n_inst + j]);
     }
-    if (total > nt->rec_cap || (c.flags & mc::kFlagRecordOverflow)) nt->overflow = true;
-    if (c.flags & mc::kFlagTimeout) return fail(MC_ERR_HIP, "a cross-tile wait timed out");
+    if (total > nt->rec_cap || (flags & mc::kFlagRecordOverflow)) nt->overflow = true;
     return MC_OK;
 }
 
@@ -678,14 +709,12 @@ int drain(mc_net *nt)
     HIP_TRY(hipMemcpyAsync(nt->h_ctl, nt->ctl, sizeof(mc::StepCtl), hipMemcpyDeviceToHost, nt->stream));
     HIP_TRY(hipStreamSynchronize(nt->stream));
     const int64_t got = std::min(nt->h_ctl->rec_total, nt->rec_cap);
-    if (got > 0) {
-        HIP_TRY(hipMemcpyAsync(nt->h_rec_id, nt->rec_id, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
-        HIP_TRY(hipMemcpyAsync(nt->h_rec_step, nt->rec_step, got * sizeof(int32_t), hipMemcpyDeviceToHost, nt->stream));
-    }
+    if (got > 0)
+        HIP_TRY(hipMemcpyAsync(nt->h_rec[0], nt->rec[0], got * sizeof(uint64_t), hipMemcpyDeviceToHost, nt->stream));
     HIP_TRY(hipMemsetAsync(&nt->ctl->rec_total, 0, sizeof(int64_t), nt->stream));
     HIP_TRY(hipMemsetAsync(&nt->ctl->flags, 0, sizeof(uint32_t), nt->stream));
     HIP_TRY(hipStreamSynchronize(nt->stream));
-    return absorb(nt, *nt->h_ctl, nt->h_rec_id, nt->h_rec_step, nt->step, nt->steps_in_flight);
+    return absorb(nt, nt->h_ctl->rec_total, nt->h_ctl->flags, nt->h_rec[0], nt->step, nt->steps_in_flight);
 }
 
 // Steps until the next drain: keep the recorder at most a quarter full at the
@@ -714,94 +743,97 @@ int run_tiled(mc_net *nt, int64_t steps)
     tn.poll_delay = nt->poll_delay;
     tn.win = nt->tiled_shape.win;
     tn.xent = nt->xent;
-    tn.abort = nt->abort_flag;
-    // Entry words are tagged with their step.  After the step index went back
-    // (checkpoint load, autotuner roll-back) the buffer may hold words of the
-    // abandoned steps with the very tags about to be polled: clear it.
+    tn.tctl = static_cast<mc::TiledCtl *>(nt->tblk);
+    tn.dropped = reinterpret_cast<unsigned long long *>(tn.tctl + 1);
+    tn.spin_limit = nt->spin_limit;
+    tn.paths = nt->paths;
+    tn.lanes = nt->lanes;
+    const int T = nt->n_tiles;
+    // Clearing is needed only in rare cases: entry words (tagged with their
+    // step) and tile words (tagged with the step mod 32767) after the step index
+    // went back (checkpoint load, tuner roll-back), tile words also after a jump
+    // ahead far enough for an old tag to come round again, and the per-launch
+    // counters after a new tiling, a checkpoint load or a failure.  A launch
+    // otherwise starts with no host-side clearing at all.
     if (nt->step < nt->xent_high)
-        HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * nt->n_tiles * nt->tile_max * sizeof(uint64_t),
-                               nt->stream));
+        HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * T * nt->tile_max * sizeof(uint64_t), nt->stream));
+    if (nt->exch_dirty || nt->step < nt->xchg_high || nt->step - nt->xchg_high > kTagSafe)
+        HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * static_cast<size_t>(T) * sizeof(uint64_t), nt->stream));
+    if (nt->exch_dirty) HIP_TRY(hipMemsetAsync(nt->tblk, 0, nt->tblk_bytes, nt->stream));
+    nt->exch_dirty = false;
     // Segments alternate between the two recorders.  After enqueueing segment k
-    // (kernel, then a copy of its counters into pinned memory) the host drains
-    // segment k-1 -- copy on the copy stream, fold into the record -- while
-    // segment k runs.
+    // (kernel, then copies of its counters and of the first part of its
+    // recorder into pinned memory) the host folds in segment k-1 while segment k
+    // runs; the recorder copy is sized from the last spike rate, and only a
+    // segment that recorded more needs a second copy.
     struct Pending {
-        int64_t s0, len;
+        int64_t s0, len, copied;
         int buf;
     };
-    Pending pend{0, 0, -1};
-    int buf = 0;
+    Pending pend{0, 0, 0, -1};
     const bool timing = nt->timing;
-    auto finish = [nt, timing](const Pending &p) -> int {
+    auto finish = [nt, timing, T](const Pending &p) -> int {
         HIP_TRY(hipEventSynchronize(nt->snap_ev[p.buf]));
-        const mc::StepCtl &c = p.buf ? *nt->h_ctl1 : *nt->h_ctl;
-        int32_t *h_ids = p.buf ? nt->h_rec_id1 : nt->h_rec_id, *h_steps = p.buf ? nt->h_rec_step1 : nt->h_rec_step;
-        const int64_t got = std::min(c.rec_total, nt->rec_cap);
-        if (got > 0) {
-            HIP_TRY(hipMemcpyAsync(h_ids, p.buf ? nt->rec_id1 : nt->rec_id, got * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                   nt->copy_stream));
-            HIP_TRY(hipMemcpyAsync(h_steps, p.buf ? nt->rec_step1 : nt->rec_step, got * sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, nt->copy_stream));
-            HIP_TRY(hipStreamSynchronize(nt->copy_stream));
-        }
+        const mc::TiledCtl &c = *static_cast<const mc::TiledCtl *>(nt->h_tblk[p.buf]);
+        const unsigned long long *dr = reinterpret_cast<const unsigned long long *>(&c + 1) + static_cast<size_t>(p.buf) * T;
         if (timing) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, nt->seg_ev0[p.buf], nt->seg_ev1[p.buf]));
             nt->kernel_ms += ms;
             nt->launches += 1;
         }
-        for (int k = 0; k < nt->n_tiles; ++k) {
-            const unsigned long long dr = nt->h_dropped[static_cast<size_t>(p.buf) * nt->n_tiles + k];
-            if (dr) nt->inst_dropped[nt->host.meta[nt->tiles_host[k].t0] >> 3] += static_cast<int64_t>(dr);
+        const int64_t total = static_cast<int64_t>(c.rec_total[p.buf]);
+        const int64_t got = std::min(total, nt->rec_cap);
+        if (got > p.copied && !(c.flags[p.buf] & mc::kFlagTimeout)) {
+            HIP_TRY(hipMemcpyAsync(nt->h_rec[p.buf] + p.copied, nt->rec[p.buf] + p.copied,
+                                   (got - p.copied) * sizeof(uint64_t), hipMemcpyDeviceToHost, nt->copy_stream));
+            HIP_TRY(hipStreamSynchronize(nt->copy_stream));
         }
+        for (int k = 0; k < T; ++k)
+            if (dr[k]) nt->inst_dropped[nt->host.meta[nt->tiles_host[k].t0] >> 3] += static_cast<int64_t>(dr[k]);
         const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
-        const int rc = absorb(nt, c, h_ids, h_steps, p.s0, p.len);
+        const int rc = absorb(nt, total, c.flags[p.buf], nt->h_rec[p.buf], p.s0, p.len);
         const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
-        adapt_segment(nt, p.len, after - before);
+        if (rc == MC_OK) {
+            nt->rec_rate = static_cast<double>(after - before) / std::max<int64_t>(1, p.len);
+            adapt_segment(nt, p.len, after - before);
+        }
         return rc;
     };
     bool first = true;
     int rc = MC_OK;
     while (steps > 0 && rc == MC_OK) {
         // the phase trace covers the first steps of the first launch of this run
-        tn.trace = first && nt->trace_tiles == nt->n_tiles ? nt->trace : nullptr;
+        tn.trace = first && nt->trace_tiles == T ? nt->trace : nullptr;
         tn.trace_steps = nt->trace_steps;
         first = false;
         const int64_t seg = std::min(steps, nt->seg_steps);
-        nt->xent_high = std::max(nt->xent_high, nt->step + seg);
-        tn.base.rec_id = buf ? nt->rec_id1 : nt->rec_id;
-        tn.base.rec_step = buf ? nt->rec_step1 : nt->rec_step;
-        tn.dropped = nt->dropped_acc + static_cast<size_t>(buf) * nt->n_tiles;
+        const int b = nt->next_buf;
+        if (++nt->epoch == 0) nt->epoch = 1;
+        tn.buf = b;
+        tn.epoch = nt->epoch;
+        tn.base.rec = nt->rec[b];
         tn.budget_ticks = nt->budget_ticks;
-        HIP_TRY(hipMemsetAsync(tn.dropped, 0, nt->n_tiles * sizeof(unsigned long long), nt->stream));
-        // Tile words from an earlier launch carry older tags; clearing them rules out
-        // a tag match across a jump of the step index (engine switch).
-        HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * nt->n_tiles * sizeof(uint64_t), nt->stream));
-        HIP_TRY(hipMemsetAsync(nt->abort_flag, 0, sizeof(uint32_t), nt->stream));
-        HIP_TRY(hipMemsetAsync(&nt->ctl->rec_total, 0, sizeof(int64_t), nt->stream));
-        HIP_TRY(hipMemsetAsync(&nt->ctl->flags, 0, sizeof(uint32_t), nt->stream));
-        if (timing) HIP_TRY(hipEventRecord(nt->seg_ev0[buf], nt->stream));
-        HIP_TRY(mc::launch_tiled(tn, nt->tiled_shape, seg, nt->stream));
-        if (timing) HIP_TRY(hipEventRecord(nt->seg_ev1[buf], nt->stream));
-        HIP_TRY(hipMemcpyAsync(buf ? nt->h_ctl1 : nt->h_ctl, nt->ctl, sizeof(mc::StepCtl), hipMemcpyDeviceToHost,
-                               nt->stream));
-        HIP_TRY(hipMemcpyAsync(nt->h_dropped + static_cast<size_t>(buf) * nt->n_tiles, tn.dropped,
-                               nt->n_tiles * sizeof(unsigned long long), hipMemcpyDeviceToHost, nt->stream));
-        HIP_TRY(hipEventRecord(nt->snap_ev[buf], nt->stream));
+        const int64_t guess = std::min<int64_t>(
+            nt->rec_cap, 4096 + static_cast<int64_t>(static_cast<double>(seg) * std::max(64.0, 2.0 * nt->rec_rate)));
+        if (timing) HIP_TRY(hipEventRecord(nt->seg_ev0[b], nt->stream));
+        HIP_TRY(mc::launch_tiled(tn, nt->tiled_shape, seg, nt->coop, nt->stream));
+        if (timing) HIP_TRY(hipEventRecord(nt->seg_ev1[b], nt->stream));
+        HIP_TRY(hipMemcpyAsync(nt->h_tblk[b], nt->tblk, nt->tblk_bytes, hipMemcpyDeviceToHost, nt->stream));
+        HIP_TRY(hipMemcpyAsync(nt->h_rec[b], nt->rec[b], guess * sizeof(uint64_t), hipMemcpyDeviceToHost, nt->stream));
+        HIP_TRY(hipEventRecord(nt->snap_ev[b], nt->stream));
+        nt->xent_high = std::max(nt->xent_high, nt->step + seg);
+        nt->xchg_high = nt->step + seg;
         if (pend.buf >= 0) rc = finish(pend);
-        pend = {nt->step, seg, buf};
-        buf ^= 1;
+        pend = {nt->step, seg, guess, b};
+        nt->next_buf ^= 1;
         nt->step += seg;
         steps -= seg;
     }
     if (pend.buf >= 0) {
-        const int rc2 = finish(pend);
-        if (rc == MC_OK) rc = rc2;
+        if (rc == MC_OK) rc = finish(pend);
+        else HIP_TRY(hipStreamSynchronize(nt->stream));
     }
-    // leave the counters at rest for the other engine and for snapshots
-    HIP_TRY(hipMemsetAsync(&nt->ctl->rec_total, 0, sizeof(int64_t), nt->stream));
-    HIP_TRY(hipMemsetAsync(&nt->ctl->flags, 0, sizeof(uint32_t), nt->stream));
-    HIP_TRY(hipStreamSynchronize(nt->stream));
     return rc;
 }
 
@@ -929,6 +961,9 @@ int restore_snapshot(mc_net *nt, const Snapshot &s)
     nt->inst_dropped = s.inst_dropped;
     nt->inst_max_step = s.inst_max_step;
     nt->max_step_spikes = s.max_step_spikes;
+    nt->exch_dirty = true;            // tile words and counters of abandoned launches
+    nt->failed = false;
+    nt->fail_msg.clear();
     return MC_OK;
 }
 
@@ -1091,15 +1126,31 @@ int autotune(mc_net *nt, int64_t trial_steps)
         }
         return MC_OK;
     };
+    const Candidate orig = pick;
+    // A failed trial leaves the state inconsistent: go back to the launch
+    // configuration and the state from before the tuner, then report.
+    auto roll_back = [&](int code) {
+        const std::string msg = g_err;
+        apply_candidate(nt, orig);
+        nt->seg_steps = seg_steps;
+        nt->timing = timing;
+        nt->overflow = false;
+        if (restore_snapshot(nt, s) != MC_OK) {
+            nt->failed = true;
+            nt->fail_msg = msg;
+        }
+        g_err = msg;
+        return code;
+    };
     for (const Candidate &c : cands)
-        if ((rc = trial(c))) return rc;
+        if ((rc = trial(c))) return roll_back(rc);
     // then the tiled engine's polling delay for the chosen tiles
     if (pick.engine == MC_ENGINE_TILED) {
         const Candidate base = pick;
         for (int d : {0, 8, 16, 24, 32, 48, 64}) {
             Candidate c = base;
             c.poll = d;
-            if ((rc = trial(c))) return rc;
+            if ((rc = trial(c))) return roll_back(rc);
         }
     }
     g_err.clear();
@@ -1169,10 +1220,15 @@ int mc_build_batch(const uint64_t *seeds, const double *scales, int32_t n, const
 int mc_run(mc_net *net, int64_t steps)
 {
     if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    LIVE_OR_FAIL(net);
     if (steps < 0) return fail(MC_ERR_ARG, "steps must be >= 0");
     if (steps == 0) return MC_OK;
     if (net->step + steps >= (int64_t{1} << 31)) return fail(MC_ERR_ARG, "step index would exceed 2^31");
     int rc = net->engine == MC_ENGINE_TILED ? run_tiled(net, steps) : run_graph(net, steps);
+    if (rc == MC_ERR_HIP) {
+        net->failed = true;
+        net->fail_msg = g_err;
+    }
     if (rc) return rc;
     if (net->overflow) {
         net->overflow = false;
@@ -1184,6 +1240,7 @@ int mc_run(mc_net *net, int64_t steps)
 int mc_get_spikes(mc_net *net, int32_t instance, int64_t *steps_out, int32_t *ids_out, int64_t cap, int64_t *count_out)
 {
     if (!net || !count_out) return fail(MC_ERR_ARG, "net and count_out must not be NULL");
+    LIVE_OR_FAIL(net);
     if (instance < 0 || instance >= net->host.n_inst) return fail(MC_ERR_ARG, "instance out of range");
     auto &v = net->unread[instance];
     *count_out = static_cast<int64_t>(v.size());
@@ -1212,8 +1269,10 @@ int mc_get_state(mc_net *net, int32_t instance, float *u_mv, float *i_pa, int32_
     int64_t nn = 0;
     int rc = mc_instance_size(net, instance, &nn, nullptr);
     if (rc) return rc;
+    LIVE_OR_FAIL(net);
     if (n != nn) return fail(MC_ERR_ARG, "n must equal the instance's neuron count");
     const int64_t o = net->host.inst_off[instance];
+    HIP_TRY(hipStreamSynchronize(net->stream));
     if (u_mv) HIP_TRY(hipMemcpy(u_mv, net->u + o, n * sizeof(float), hipMemcpyDeviceToHost));
     if (i_pa) HIP_TRY(hipMemcpy(i_pa, net->cur + o, n * sizeof(float), hipMemcpyDeviceToHost));
     if (refr) {
@@ -1229,8 +1288,10 @@ int mc_set_state(mc_net *net, int32_t instance, const float *u_mv, const float *
     int64_t nn = 0;
     int rc = mc_instance_size(net, instance, &nn, nullptr);
     if (rc) return rc;
+    LIVE_OR_FAIL(net);
     if (n != nn) return fail(MC_ERR_ARG, "n must equal the instance's neuron count");
     const int64_t o = net->host.inst_off[instance];
+    HIP_TRY(hipStreamSynchronize(net->stream));
     if (u_mv) HIP_TRY(hipMemcpy(net->u + o, u_mv, n * sizeof(float), hipMemcpyHostToDevice));
     if (i_pa) HIP_TRY(hipMemcpy(net->cur + o, i_pa, n * sizeof(float), hipMemcpyHostToDevice));
     if (refr) {
@@ -1248,10 +1309,10 @@ int mc_get_counters(mc_net *net, int32_t instance, mc_counters *out)
 {
     if (!net || !out) return fail(MC_ERR_ARG, "net and out must not be NULL");
     if (instance < -1 || instance >= net->host.n_inst) return fail(MC_ERR_ARG, "instance out of range");
+    LIVE_OR_FAIL(net);
     std::vector<unsigned long long> acc(static_cast<size_t>(net->pois_slots));
+    HIP_TRY(hipStreamSynchronize(net->stream));
     HIP_TRY(hipMemcpy(acc.data(), net->pois_acc, acc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-    mc::StepCtl c{};
-    HIP_TRY(hipMemcpy(&c, net->ctl, sizeof(c), hipMemcpyDeviceToHost));
     out->steps = net->step;
     out->spikes = 0;
     out->events = 0;
@@ -1299,6 +1360,8 @@ int mc_get_csr(mc_net *net, int32_t instance, int64_t *row_ptr, int32_t *post, i
     int rc = mc_instance_size(net, instance, &nn, &mm);
     if (rc) return rc;
     if (n_synapses != mm) return fail(MC_ERR_ARG, "n_synapses must equal the instance's synapse count");
+    LIVE_OR_FAIL(net);
+    HIP_TRY(hipStreamSynchronize(net->stream));
     const int64_t o = net->host.inst_off[instance];
     const int64_t so = net->host.inst_syn_off[instance];
     if (row_ptr) {
@@ -1331,6 +1394,7 @@ int mc_get_csr(mc_net *net, int32_t instance, int64_t *row_ptr, int32_t *post, i
 int mc_set_launch(mc_net *net, const mc_launch *l)
 {
     if (!net || !l) return fail(MC_ERR_ARG, "net and l must not be NULL");
+    LIVE_OR_FAIL(net);
     if (l->engine < 0 || l->engine > MC_ENGINE_TILED) return fail(MC_ERR_ARG, "unknown engine");
     if (l->tile && (l->tile < 16 || l->tile > 4096)) return fail(MC_ERR_ARG, "tile must be in [16, 4096]");
     if (l->ring < 0 || l->ring > 2) return fail(MC_ERR_ARG, "ring must be 0 (auto), 1 (LDS) or 2 (global)");
@@ -1339,6 +1403,8 @@ int mc_set_launch(mc_net *net, const mc_launch *l)
     if (l->block && l->block != 64 && l->block != 128 && l->block != 256 && l->block != 512) return fail(MC_ERR_ARG, "block must be 64, 128, 256 or 512");
     if (l->deliver_grid < 0) return fail(MC_ERR_ARG, "deliver_grid must be >= 1");
     if (l->poll_delay < -1 || l->poll_delay > 255) return fail(MC_ERR_ARG, "poll_delay must be -1 or in [1, 255]");
+    if (l->coop < 0 || l->coop > 2) return fail(MC_ERR_ARG, "coop must be 0 (keep), 1 (cooperative) or 2 (ordinary)");
+    if (l->coop) net->coop = l->coop == 1;
     if (l->poll_delay) {
         net->poll_delay = l->poll_delay < 0 ? 0 : l->poll_delay;
         net->poll_delay_set = true;
@@ -1433,6 +1499,7 @@ int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t 
     int64_t nn = 0;
     int rc = mc_instance_size(net, instance, &nn, nullptr);
     if (rc) return rc;
+    LIVE_OR_FAIL(net);
     if (count < 0 || count > (int64_t{1} << 30)) return fail(MC_ERR_ARG, "count out of range");
     if (count > 0 && !ids) return fail(MC_ERR_ARG, "ids must not be NULL");
     const int32_t off = net->host.inst_off[instance];
@@ -1465,6 +1532,7 @@ int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t 
         tn.subrow = net->subrow;
         tn.syn = net->syn;
         tn.syn_fmt = net->syn_fmt;
+        tn.lanes = net->lanes;
         int first = 0;
         while (net->tiles_host[first].inst_n0 != off) ++first;
         const int threads = 1024;   // events, not neurons, spread over the threads: more loads in flight
@@ -1506,12 +1574,14 @@ int mc_tune(mc_net *net, int64_t trial_steps)
 {
     if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
     if (trial_steps < 1 || trial_steps > 100000) return fail(MC_ERR_ARG, "trial_steps must be in [1, 100000]");
+    LIVE_OR_FAIL(net);
     return autotune(net, trial_steps);
 }
 
 int mc_save_state(mc_net *net, const char *path)
 {
     if (!net || !path) return fail(MC_ERR_ARG, "net and path must not be NULL");
+    LIVE_OR_FAIL(net);
     return write_checkpoint(net, path);
 }
 
@@ -1519,6 +1589,41 @@ int mc_load_state(mc_net *net, const char *path)
 {
     if (!net || !path) return fail(MC_ERR_ARG, "net and path must not be NULL");
     return read_checkpoint(net, path);
+}
+
+int mc_probe(int32_t kind, int64_t bytes, double *rate, double *kernel_ms)
+{
+    if (!rate) return fail(MC_ERR_ARG, "rate must not be NULL");
+    if (kind < MC_PROBE_HBM_COPY || kind > MC_PROBE_DEVICE_ATOMICS) return fail(MC_ERR_ARG, "unknown probe");
+    if (kind != MC_PROBE_LDS_ATOMICS && (bytes < 8192 || bytes > (int64_t{1} << 36)))
+        return fail(MC_ERR_ARG, "bytes must be in [8 KiB, 64 GiB]");
+    double ms = 0.0;
+    const hipError_t e = mc::run_probe(kind, bytes, rate, &ms);
+    if (kernel_ms) *kernel_ms = ms;
+    if (e == hipErrorOutOfMemory) return fail(MC_ERR_NOMEM, "probe buffer: out of device memory");
+    if (e != hipSuccess) return fail(MC_ERR_HIP, std::string("probe: ") + hipGetErrorString(e));
+    return MC_OK;
+}
+
+int mc_get_paths(mc_net *net, int64_t *counts, int32_t n)
+{
+    if (!net || !counts) return fail(MC_ERR_ARG, "net and counts must not be NULL");
+    if (n < 1) return fail(MC_ERR_ARG, "n must be >= 1");
+    unsigned long long c[mc::kPaths] = {};
+    if (net->paths) {
+        HIP_TRY(hipStreamSynchronize(net->stream));
+        HIP_TRY(hipMemcpy(c, net->paths, sizeof(c), hipMemcpyDeviceToHost));
+    }
+    for (int32_t k = 0; k < n; ++k) counts[k] = k < mc::kPaths ? static_cast<int64_t>(c[k]) : 0;
+    return MC_OK;
+}
+
+int mc_set_wait_limit(mc_net *net, int64_t polls)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (polls < 0 || polls > int64_t{0xFFFFFFFF}) return fail(MC_ERR_ARG, "polls must be in [0, 2^32 - 1]");
+    net->spin_limit = static_cast<uint32_t>(polls);
+    return MC_OK;
 }
 
 void mc_free(mc_net *net) { release(net); }

@@ -163,8 +163,7 @@ __global__ __launch_bounds__(BLOCK) void k_neuron(DevNet P, int s_off)
             const int rank = __popcll(mask & ((1ull << lane) - 1ull));
             const int64_t pos = ctl->rec_total + static_cast<int64_t>(old >> 40) + rank;
             if (pos < P.rec_cap) {
-                P.rec_id[pos] = i;
-                P.rec_step[pos] = static_cast<int32_t>(n);
+                P.rec[pos] = rec_entry(n, i);
             } else {
                 atomicOr(&ctl->flags, kFlagRecordOverflow);
             }
@@ -296,21 +295,25 @@ hipError_t launch_clear_i32(int32_t *p, int64_t n, hipStream_t st)
 //      the LDS ring with LDS integer atomics.
 //
 // Exchange protocol: each tile owns one 64-bit word per step parity,
-//     bits 63..62 tag ((n >> 1) & 1) + 1, 61..48 spike count,
-//     47..0 the offsets in the tile (12 bits each, tiles <= 4096) of its
-//     first four spikes, first at bits 47..36,
-// and, for its 5th, 6th, ... spikes, 64-bit entry words (tag32 = n + 1 | id);
-// at full scale a tile almost never spikes more than four times in a step, so
+//     bits 63..49 tag (n mod 32767) + 1, 48..36 spike count,
+//     35..0 the offsets in the tile (12 bits each, tiles <= 4096) of its
+//     first three spikes, first at bits 35..24,
+// and, for its 4th, 5th, ... spikes, 64-bit entry words (tag32 = n + 1 | id);
+// at full scale a tile almost never spikes more than three times in a step, so
 // a step's ids arrive with the words and no entry has to be read.
 // Words are written and polled with relaxed agent-scope atomics; a reader
 // accepts a word only when its tag matches, so no fence or counter is needed:
 // an aligned store is seen whole or not at all.  A tile cannot publish step
 // n+2 (same parity) before it has seen every tile's step n+1 word, which every
-// tile writes only after finishing its reads of step n, so the tag only has to
-// tell step n from step n-2 and from the zero the buffers start each launch
-// with.  The words of a step are polled by every tile of the instance; polling
-// starts after a short sleep, since polls issued while the last tiles'
-// stores are still in flight only congest the lines those stores go to.
+// tile writes only after finishing its reads of step n, so within a launch the
+// tag only has to tell step n from step n-2.  Between launches the words keep
+// the tags of the last steps run; the host clears them only when the step
+// index moved back (checkpoint load, tuner roll-back) or jumped so far ahead
+// that an old tag could come round again, so a launch normally starts with no
+// clearing at all.  The words of a step are polled by every tile of the
+// instance; polling starts after a short sleep, since polls issued while the
+// last tiles' stores are still in flight only congest the lines those stores
+// go to.
 // ===========================================================================
 namespace mc {
 namespace {
@@ -318,11 +321,11 @@ namespace {
 constexpr int kSpkBatch = 2048;              // spikes processed per delivery batch
 constexpr int kSrcDirect = 16;               // most spikes of a tile mapped to their place one by one
 constexpr int kGroupMin = 8;                 // fewest lanes per spike for delivery by fixed lane groups
-constexpr int kWordIds = 4;                  // spike offsets carried by a tile's word
+constexpr int kWordIds = 3;                  // spike offsets carried by a tile's word
 constexpr int kDeliverU = 4;                 // records in flight per thread in the step kernel's delivery
+constexpr int kCursorU = 8;                  // and with a cursor over many spikes
 constexpr int kInjectU = 8;                  // and in the injection kernel
 constexpr int kInjBatch = 2048;              // spikes per batch of the injection kernel
-constexpr uint32_t kSpinLimit = 1u << 24;    // polls before a wait gives up
 
 // Exclusive prefix sum of one value per thread, in thread order; returns the
 // exclusive prefix and writes the block total to *total.  s_wave: >= 17 ints.
@@ -407,20 +410,43 @@ __device__ __forceinline__ void store_word(W *p, W v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Poll *p until `accept(word)`; false if the wait was abandoned (time-out or
-// another workgroup gave up).
-template <class W, class Accept>
-__device__ __forceinline__ bool wait_word(const W *p, uint32_t *abort, StepCtl *ctl, Accept accept, W &w)
+// Tile word of step n: bits 63..49 a tag from the step index ((n mod 32767) + 1,
+// never 0), 48..36 the tile's spike count, then the 12-bit offsets in the tile
+// of its first three spikes from bit 35 down.
+__device__ __forceinline__ uint64_t word_tag(int64_t n) { return static_cast<uint64_t>(n % 32767) + 1u; }
+__device__ __forceinline__ bool word_is(uint64_t w, uint64_t tag) { return (w >> 49) == tag; }
+__device__ __forceinline__ int word_count(uint64_t w) { return static_cast<int>((w >> 36) & 0x1FFFu); }
+__device__ __forceinline__ int word_offset(uint64_t w, int k) { return static_cast<int>((w >> (24 - 12 * k)) & 0xFFFu); }
+__device__ __forceinline__ uint64_t word_make(uint64_t tag, int count) { return (tag << 49) | (static_cast<uint64_t>(count) << 36); }
+
+// Give up the launch: name it in the abort word (the other workgroups' waits
+// see it and give up too) and flag the time-out for the host.
+__device__ __forceinline__ void give_up(const TiledNet &P)
 {
+    __hip_atomic_store(&P.tctl->abort_epoch, P.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicOr(&P.tctl->flags[P.buf], kFlagTimeout);
+}
+
+// Poll *p until `accept(word)`; false if the wait was abandoned: after
+// spin_limit polls (checked every 1024; a limit of 0 gives up at once, which
+// lets the host test the failure path), or when another workgroup of this
+// launch gave up.
+template <class W, class Accept>
+__device__ __forceinline__ bool wait_word(const W *p, const TiledNet &P, Accept accept, W &w)
+{
+    if (P.spin_limit == 0) {
+        give_up(P);
+        return false;
+    }
     uint32_t spins = 0;
     for (;;) {
         w = load_word(p);
         if (accept(w)) return true;
         if ((++spins & 1023u) == 0) {
-            if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-            if (spins > kSpinLimit) {
-                __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                atomicOr(&ctl->flags, kFlagTimeout);
+            if (__hip_atomic_load(&P.tctl->abort_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == P.epoch)
+                return false;
+            if (spins > P.spin_limit) {
+                give_up(P);
                 return false;
             }
         }
@@ -515,6 +541,58 @@ __device__ __forceinline__ unsigned long long deliver_grouped(const void *__rest
     return r < len ? static_cast<unsigned long long>((len - r + group - 1) / group) : 0ull;
 }
 
+// Add the events of nb spikes, spike q's sub-row being records s_beg[q] ..
+// s_beg[q] + s_len[q] - 1, with groups of G lanes: group g (of nthr / G) takes
+// spikes g, g + groups, ..., and lane r of a group takes records r, r + G, ...
+// of each of them.  Each lane walks its (spike, record) items with a cursor
+// and keeps U records in flight, so there is neither a scan of the lengths
+// nor a search for an event's spike; the work is balanced when G is about the
+// mean sub-row length.  Returns the records this thread added.
+template <int SF, int U, class Add>
+__device__ __forceinline__ unsigned long long deliver_cursor(const void *__restrict__ syn, const int *s_beg,
+                                                             const int *s_len, int nb, int G, Add add)
+{
+    const int l = threadIdx.x, groups = static_cast<int>(blockDim.x) / G;
+    int q = l / G;
+    const int r = l - q * G;
+    if (q >= groups) return 0;                         // lanes past the last whole group
+    int j = r, len = q < nb ? s_len[q] : 0;
+    while (q < nb && j >= len) {
+        q += groups;
+        len = q < nb ? s_len[q] : 0;
+    }
+    unsigned long long done = 0;
+    while (q < nb) {
+        uint32_t idx[U];
+        bool v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            v[k] = q < nb;
+            idx[k] = v[k] ? static_cast<uint32_t>(s_beg[q] + j) : 0u;
+            if (v[k]) {
+                j += G;
+                while (j >= len) {                     // on to this group's next spike with a record r
+                    q += groups;
+                    if (q >= nb) break;
+                    len = s_len[q];
+                    j = r;
+                }
+            }
+        }
+        int wq[U], tg[U], d[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (v[k]) wq[k] = syn_record<SF>(syn, idx[k], tg[k], d[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (v[k]) {
+                add(tg[k], d[k], wq[k]);
+                ++done;
+            }
+    }
+    return done;
+}
+
 // Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b mod 8),
 // each XCD with its own L2.  Workgroup b takes tile rank(b) in the order
 // (b mod 8, b / 8), so that every XCD holds a contiguous run of tiles: the
@@ -546,6 +624,8 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     __shared__ int s_big;                              // step in which some tile sent over kSrcDirect spikes
     __shared__ int s_many;                             // step in which some tile sent over kWordIds spikes
     __shared__ long long s_recbase;
+    __shared__ unsigned long long s_drop;              // events dropped by the step budget (this launch)
+    __shared__ uint32_t s_paths[kPaths];               // tile-steps per delivery path (this launch)
 
     const DevNet &B = P.base;
     StepCtl *ctl = B.ctl;
@@ -593,6 +673,8 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         s_abort = 0;
         s_big = -1;
         s_many = -1;
+        s_drop = 0;
+        for (int k = 0; k < kPaths; ++k) s_paths[k] = 0;
     }
 
     // The tile lies in one instance: its seed and local numbering are uniform.
@@ -632,7 +714,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         }
     }
     int64_t n = ctl->nbase;
-    int64_t rec_base = ctl->rec_total;
+    int64_t rec_base = 0;                              // this launch's recorder starts empty
     unsigned long long ev_acc = 0, pois_sum = 0, drop_acc = 0;
     auto counts = [&](int64_t m) {
         const uint64_t *src = s_blk + static_cast<size_t>(m & 1) * 4 * nbk;
@@ -663,7 +745,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     uint64_t *tr = nullptr;
     for (int64_t s = 0; s < steps; ++s, ++n) {
         const int par = static_cast<int>(n & 1);
-        const uint64_t tag2 = static_cast<uint64_t>((n >> 1) & 1) + 1u;
+        const uint64_t tag15 = word_tag(n);
         const uint64_t tag32 = static_cast<uint64_t>(static_cast<uint32_t>(n + 1));
         uint64_t *words = P.xchg + static_cast<size_t>(par) * P.n_tiles + td.itile0;
         uint64_t *entries = P.xent + (static_cast<size_t>(par) * P.n_tiles + td.itile0) * tmax;
@@ -727,11 +809,11 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         int nspk;
         int pos = block_scan_excl(nmine, s_wave, &nspk);
         if (NPT == 1 && l == 0) {
-            uint64_t w = (tag2 << 62) | (static_cast<uint64_t>(nspk) << 48);
+            uint64_t w = word_make(tag15, nspk);
             const int nw = min(nspk, kWordIds);
             for (int q = 0, got = 0; got < nw; ++q) {
                 for (uint64_t m = s_mask[q]; m && got < nw; m &= m - 1, ++got)
-                    w |= static_cast<uint64_t>(q * 64 + __builtin_ctzll(m)) << (36 - 12 * got);
+                    w |= static_cast<uint64_t>(q * 64 + __builtin_ctzll(m)) << (24 - 12 * got);
             }
             store_word(words + tl, w);
         }
@@ -748,9 +830,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         if (NPT != 1) {
             __syncthreads();
             if (l == 0) {
-                uint64_t w = (tag2 << 62) | (static_cast<uint64_t>(nspk) << 48);
+                uint64_t w = word_make(tag15, nspk);
                 for (int k = 0; k < min(nspk, kWordIds); ++k)
-                    w |= static_cast<uint64_t>(s_own[k] - t0) << (36 - 12 * k);
+                    w |= static_cast<uint64_t>(s_own[k] - t0) << (24 - 12 * k);
                 store_word(words + tl, w);
             }
         }
@@ -763,8 +845,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         const bool rec_reserve = NPT > 1 && T != P.n_tiles && nspk > 0 && l == nthr - 1;
         unsigned long long rec_reserved = 0;
         if (rec_reserve)
-            rec_reserved = atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->rec_total),
-                                     static_cast<unsigned long long>(nspk));
+            rec_reserved = atomicAdd(&P.tctl->rec_total[P.buf], static_cast<unsigned long long>(nspk));
         // ---- 3. background input: blocks of step n + 2 into the buffer whose
         // blocks (step n) were all turned into counts before the last barrier;
         // counts of step n + 1 from blocks drawn in the previous step -----------
@@ -780,12 +861,8 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         auto record_reserved = [&]() {
             for (int q = l; q < nspk; q += nthr) {
                 const int64_t at = s_recbase + q;
-                if (at < B.rec_cap) {
-                    B.rec_id[at] = s_own[q];
-                    B.rec_step[at] = static_cast<int32_t>(n);
-                } else {
-                    atomicOr(&ctl->flags, kFlagRecordOverflow);
-                }
+                if (at < B.rec_cap) B.rec[at] = rec_entry(n, s_own[q]);
+                else atomicOr(&P.tctl->flags[P.buf], kFlagRecordOverflow);
             }
         };
         // a range reserved before the wait is filled even when the wait is
@@ -803,15 +880,15 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             int c = 0;
             if (l < T) {
                 uint64_t w = 0;
-                if (wait_word(words + l, P.abort, ctl, [tag2](uint64_t x) { return (x >> 62) == tag2; }, w)) {
-                    c = static_cast<int>((w >> 48) & 0x3FFFu);
+                if (wait_word(words + l, P, [tag15](uint64_t x) { return word_is(x, tag15); }, w)) {
+                    c = word_count(w);
                     s_word[l] = w;
                     if (NPT == 1) {
                         nk = min(c, kWordIds);
                         const int64_t sub_l = td.sub_base + static_cast<int64_t>(l) * td.stride * T;
 #pragma unroll
                         for (int k = 0; k < kWordIds; ++k)
-                            if (k < nk) sr_first[k] = P.subrow[sub_l + static_cast<int64_t>((w >> (36 - 12 * k)) & 0xFFFu) * T];
+                            if (k < nk) sr_first[k] = P.subrow[sub_l + static_cast<int64_t>(word_offset(w, k)) * T];
                     }
                 } else {
                     s_abort = 1;
@@ -842,11 +919,11 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         } else {
             for (int q = l; q < T; q += nthr) {
                 uint64_t w = 0;
-                if (!wait_word(words + q, P.abort, ctl, [tag2](uint64_t x) { return (x >> 62) == tag2; }, w)) {
+                if (!wait_word(words + q, P, [tag15](uint64_t x) { return word_is(x, tag15); }, w)) {
                     s_abort = 1;
                     break;
                 }
-                s_cnt[q] = static_cast<int>((w >> 48) & 0x3FFFu);
+                s_cnt[q] = word_count(w);
                 s_word[q] = w;
             }
             __syncthreads();
@@ -867,24 +944,21 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         if (T == P.n_tiles) {
             for (int q = l; q < nspk; q += nthr) {
                 const int64_t at = rec_base + s_cnt[tl] + q;
-                if (at < B.rec_cap) {
-                    B.rec_id[at] = s_own[q];
-                    B.rec_step[at] = static_cast<int32_t>(n);
-                } else {
-                    atomicOr(&ctl->flags, kFlagRecordOverflow);
-                }
+                if (at < B.rec_cap) B.rec[at] = rec_entry(n, s_own[q]);
+                else atomicOr(&P.tctl->flags[P.buf], kFlagRecordOverflow);
             }
             rec_base += S;
         } else if (nspk) {
             if (NPT == 1) {
                 if (l == 0)
-                    s_recbase = static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->rec_total),
+                    s_recbase = static_cast<long long>(atomicAdd(&P.tctl->rec_total[P.buf],
                                                                  static_cast<unsigned long long>(nspk)));
                 __syncthreads();
             }   // else reserved before the wait (s_recbase written before its barrier)
             record_reserved();
         }
         // ---- 5. delivery into this tile's ring ----------------------------------
+        if (S == 0 && l == 0) s_paths[kPathNoSpikes] += 1;
         for (int b0 = 0; b0 < S; b0 += kSpkBatch) {
             const int nb = min(kSpkBatch, S - b0);
             // every tile at most kWordIds spikes: the sub-rows are in the pollers'
@@ -904,10 +978,10 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                     src = find_segment(s_cnt, T + 1, g);
                     k = g - s_cnt[src];
                 }
-                int pre = td.inst_n0 + src * td.stride + static_cast<int>((s_word[src] >> (36 - 12 * min(k, 3))) & 0xFFFu);
+                int pre = td.inst_n0 + src * td.stride + word_offset(s_word[src], min(k, kWordIds - 1));
                 if (k >= kWordIds) {
                     uint64_t w = 0;
-                    if (!wait_word(entries + static_cast<size_t>(src) * tmax + k, P.abort, ctl,
+                    if (!wait_word(entries + static_cast<size_t>(src) * tmax + k, P,
                                    [tag32](uint64_t x) { return (x >> 32) == tag32; }, w)) {
                         s_abort = 1;
                         w = static_cast<uint32_t>(td.inst_n0);
@@ -917,6 +991,13 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 return P.subrow[td.sub_base + static_cast<int64_t>(pre - td.inst_n0) * T];
             };
             const bool grouped = fast && !BUDGET && nb * kGroupMin <= nthr;
+            // delivery-path counters (the choice is uniform over the workgroup)
+            if (l == 0) {
+                s_paths[grouped ? kPathGrouped : fast ? kPathFast : nb <= nthr ? kPathPerThread : kPathBatched] += 1;
+                if (b0 > 0) s_paths[kPathExtraBatch] += 1;
+                if (!fast) s_paths[direct ? kPathDirectMap : kPathSearch] += 1;
+                if (s_many == static_cast<int>(n)) s_paths[kPathEntryWords] += 1;
+            }
             if (grouped) {
                 if (l < T) {
 #pragma unroll
@@ -928,33 +1009,40 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 }
                 __syncthreads();
             } else if (fast) {
-                int len = 0;
+                // s_pre: the sub-row lengths, or (step budget) their exclusive prefix
+                int run = 0, total = 0;
+                if (BUDGET) {
+                    int len = 0;
 #pragma unroll
-                for (int k = 0; k < kWordIds; ++k)
-                    if (k < nk) len += static_cast<int>(sr_first[k].y);
-                int total;
-                int run = block_scan_excl(len, s_wave, &total);
+                    for (int k = 0; k < kWordIds; ++k)
+                        if (k < nk) len += static_cast<int>(sr_first[k].y);
+                    run = block_scan_excl(len, s_wave, &total);
+                }
 #pragma unroll
                 for (int k = 0; k < kWordIds; ++k)
                     if (k < nk) {
                         s_beg[ex_l + k] = static_cast<int>(sr_first[k].x);
-                        s_pre[ex_l + k] = run;
+                        s_pre[ex_l + k] = BUDGET ? run : static_cast<int>(sr_first[k].y);
                         run += static_cast<int>(sr_first[k].y);
                     }
-                if (l == 0) s_pre[nb] = total;
+                if (BUDGET && l == 0) s_pre[nb] = total;
                 __syncthreads();
             } else if (nb <= nthr) {
-                // one spike per thread: scan the sub-row lengths from the registers
+                // one spike per thread
                 int len = 0;
                 if (l < nb) {
                     const uint2 sr = subrow_of(l);
                     s_beg[l] = static_cast<int>(sr.x);
                     len = static_cast<int>(sr.y);
                 }
-                int total;
-                const int ex = block_scan_excl(len, s_wave, &total);
-                if (l < nb) s_pre[l] = ex;
-                if (l == 0) s_pre[nb] = total;
+                if (BUDGET) {
+                    int total;
+                    const int ex = block_scan_excl(len, s_wave, &total);
+                    if (l < nb) s_pre[l] = ex;
+                    if (l == 0) s_pre[nb] = total;
+                } else if (l < nb) {
+                    s_pre[l] = len;
+                }
                 __syncthreads();
                 if (s_abort) break;
             } else {
@@ -965,7 +1053,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 }
                 __syncthreads();
                 if (s_abort) break;
-                lds_scan_excl(s_pre, nb, s_wave);
+                if (BUDGET) lds_scan_excl(s_pre, nb, s_wave);
             }
             if (tr && b0 == 0) tr[5] = __builtin_amdgcn_s_memrealtime();
             auto add = [&](int tg, int d, int wq) {
@@ -983,11 +1071,12 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             };
             if (grouped) {
                 ev_acc += deliver_grouped<SF, kDeliverU>(P.syn, s_beg, s_pre, nb, add);
+            } else if (!BUDGET) {
+                ev_acc += deliver_cursor<SF, kCursorU>(P.syn, s_beg, s_pre, nb, P.lanes, add);
             } else {
                 const int E = s_pre[nb];
                 if (l == 0) ev_acc += static_cast<unsigned long long>(E);
-                deliver_events<SF, kDeliverU>(P.syn, s_beg, s_pre, nb, E, add, t_step, BUDGET ? P.budget_ticks : 0u,
-                                              &drop_acc);
+                deliver_events<SF, kDeliverU>(P.syn, s_beg, s_pre, nb, E, add, t_step, P.budget_ticks, &drop_acc);
             }
             __syncthreads();
         }
@@ -1034,11 +1123,23 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     }
     if ((l & 63) == 0 && ev && !s_abort) atomicAdd(&ctl->events, ev);
     if ((l & 63) == 0 && ps) atomicAdd(&B.pois_acc[t], ps);
-    if (BUDGET && (l & 63) == 0 && dr) atomicAdd(&P.dropped[t], dr);
-    if (l == 0 && !s_abort) {
+    if (BUDGET) {
+        if ((l & 63) == 0 && dr) atomicAdd(&s_drop, dr);
+        __syncthreads();
+    }
+    if (l == 0)
+        for (int k = 0; k < kPaths; ++k)
+            if (s_paths[k]) atomicAdd(&P.paths[k], static_cast<unsigned long long>(s_paths[k]));
+    if (l == 0) {
+        // this launch's counters: the events this tile dropped (every launch
+        // writes its own, so nothing is cleared in between) ...
+        P.dropped[static_cast<size_t>(P.buf) * P.n_tiles + t] = BUDGET ? s_drop : 0ull;
         if (t == 0) {
-            ctl->nbase = n;
-            if (T == P.n_tiles) ctl->rec_total = rec_base;
+            if (!s_abort) ctl->nbase = n;
+            if (T == P.n_tiles) P.tctl->rec_total[P.buf] = static_cast<unsigned long long>(rec_base);
+            // ... and the other buffer's counters, zeroed for the next launch
+            P.tctl->rec_total[P.buf ^ 1] = 0;
+            P.tctl->flags[P.buf ^ 1] = 0;
         }
     }
 }
@@ -1181,14 +1282,16 @@ hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, cons
     return hipGetLastError();
 }
 
-hipError_t launch_tiled(const TiledNet &tn, const TiledShape &sh, int64_t steps, hipStream_t st)
+hipError_t launch_tiled(const TiledNet &tn, const TiledShape &sh, int64_t steps, bool coop, hipStream_t st)
 {
     TiledNet arg = tn;
     int64_t nsteps = steps;
     void *args[] = {&arg, &nsteps};
     const int mode = (tn.budget_ticks != 0 ? 1 : 0) | (tn.trace != nullptr ? 2 : 0);
-    return hipLaunchCooperativeKernel(tiled_kernel(tn.syn_fmt, sh.lds_ring, sh.npt, mode), dim3(tn.n_tiles),
-                                      dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
+    const void *f = tiled_kernel(tn.syn_fmt, sh.lds_ring, sh.npt, mode);
+    if (coop)
+        return hipLaunchCooperativeKernel(f, dim3(tn.n_tiles), dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
+    return hipLaunchKernel(f, dim3(tn.n_tiles), dim3(sh.threads), args, static_cast<unsigned>(sh.lds), st);
 }
 
 }  // namespace mc
@@ -1208,7 +1311,6 @@ template <int SF>
 __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t *ids, int32_t count, int64_t n)
 {
     extern __shared__ int lds[];
-    __shared__ int s_wave[17];
     const DevNet &B = P.base;
     const int t = blockIdx.x + P.tile_offset;         // tiles of one instance
     const TileDesc td = P.tiles[t];
@@ -1217,7 +1319,7 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     const int tmax = P.tile_max, tlen = td.len;
     int *ring = lds;                                  // [R][tmax]
     int *s_beg = ring + R * tmax;                     // [kInjBatch]
-    int *s_pre = s_beg + kInjBatch;                   // [kInjBatch + 1]
+    int *s_len = s_beg + kInjBatch;                   // [kInjBatch]
     for (int q = l; q < R * tmax; q += nthr) ring[q] = 0;
     __syncthreads();
     for (int b0 = 0; b0 < count; b0 += kInjBatch) {
@@ -1225,12 +1327,10 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
         for (int q = l; q < nb; q += nthr) {
             const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(ids[b0 + q] - td.inst_n0) * td.intiles];
             s_beg[q] = static_cast<int>(sr.x);
-            s_pre[q] = static_cast<int>(sr.y);
+            s_len[q] = static_cast<int>(sr.y);
         }
         __syncthreads();
-        lds_scan_excl(s_pre, nb, s_wave);
-        const int E = s_pre[nb];
-        deliver_events<SF, kInjectU>(P.syn, s_beg, s_pre, nb, E, [&](int tg, int d, int wq) {
+        deliver_cursor<SF, kInjectU>(P.syn, s_beg, s_len, nb, P.lanes, [&](int tg, int d, int wq) {
             atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, wq);
         });
         __syncthreads();

@@ -50,9 +50,24 @@ struct DevNet {
     StepCtl *ctl;
     uint64_t *work;                   // delivery work items: pre << 32 | chunk
     unsigned long long *pois_acc;     // per-block Poisson event sums
-    int32_t *rec_id;
-    int32_t *rec_step;
+    uint64_t *rec;                    // spike recorder: step << 32 | neuron id
     int64_t rec_cap;
+};
+
+// Spike record entry: step index (< 2^31) in the high word, global neuron id in the low.
+__host__ __device__ inline uint64_t rec_entry(int64_t step, int32_t id)
+{
+    return (static_cast<uint64_t>(static_cast<uint32_t>(step)) << 32) | static_cast<uint32_t>(id);
+}
+
+// Per-launch counters of the tiled engine.  Launches alternate between two
+// recorder buffers; each set is zeroed by the launch that uses the other buffer,
+// so the host never clears them between launches.
+struct TiledCtl {
+    unsigned long long rec_total[2];  // spikes recorded into buffer b by the launch using it
+    uint32_t flags[2];                // kFlag* of the launch using buffer b
+    uint32_t abort_epoch;             // epoch of a launch in which a wait gave up
+    uint32_t pad;
 };
 
 // Tiled persistent engine.  Tiles are ranges of consecutive neurons that never
@@ -88,21 +103,43 @@ struct TiledNet {
     const void *syn;                  // packed synapse records (SynFmt), CSR order
     int32_t syn_fmt;
     int32_t poll_delay;               // sleep before the first poll of a step, in units of 64 clocks
-    uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first four offsets)
+    uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first three offsets)
     uint64_t *xent;                   // [2][n_tiles][tile_max] further spike ids (tag32 | id)
-    uint32_t *abort;                  // set when a wait gives up
+    TiledCtl *tctl;                   // per-launch counters, abort word
+    int32_t buf;                      // recorder buffer of this launch (0 or 1)
+    uint32_t epoch;                   // launch number (never 0): the abort word names the launch
+    uint32_t spin_limit;              // polls before a wait gives up (0: at once)
     uint64_t *trace;                  // optional [trace_steps][n_tiles][8] phase timestamps
     int32_t trace_steps;
     int32_t gstride;                  // global-ring variant: ints per slot row (multiple of 32)
-    unsigned long long *dropped;      // [n_tiles] events dropped by the step budget (this launch)
+    unsigned long long *dropped;      // [2][n_tiles] events dropped by the step budget, per buffer
+    unsigned long long *paths;        // [kPaths] tile-steps per delivery path, summed over launches
     uint32_t budget_ticks;            // step budget in 100 MHz clock ticks; 0: none
     int32_t win;                      // global-ring variant: LDS window of the nearest `win` slots (< R)
+    int32_t lanes;                    // lanes per spike when a step's spikes are delivered with a cursor
+                                      // (about the mean sub-row length)
     int32_t *gring;                   // global-ring variant: [n_tiles][R][gstride], one slice per workgroup
 };
 
 constexpr int kTraceSlots = 8;             // timestamps per (step, tile)
 
+// Delivery paths of the tiled step kernel, counted per tile and step (a step
+// with several spike batches counts each batch).
+enum DeliveryPath : int {
+    kPathNoSpikes = 0,      // no spike in the instance this step
+    kPathGrouped = 1,       // ids from the tile words, fixed lane groups per spike
+    kPathFast = 2,          // ids from the tile words, events spread by a length scan
+    kPathPerThread = 3,     // one spike per thread: ids looked up, sub-row read here
+    kPathBatched = 4,       // more spikes than threads: looked up in a strided loop
+    kPathExtraBatch = 5,    // a spike batch after the first (more than 2048 spikes)
+    kPathDirectMap = 6,     // looked-up ids placed by the per-tile map
+    kPathSearch = 7,        // looked-up ids placed by a binary search over the tile offsets
+    kPathEntryWords = 8,    // some tile sent more spikes than its word carries
+    kPaths = 9
+};
+
 constexpr uint32_t kFlagTimeout = 2u;      // a cross-tile wait gave up
+constexpr uint32_t kSpinLimitDefault = 1u << 24;   // polls before a cross-tile wait gives up
 
 hipError_t launch_neuron(const DevNet &d, int block, int s_off, hipStream_t st);
 hipError_t launch_deliver(const DevNet &d, int grid, int s_off, hipStream_t st);
@@ -120,7 +157,11 @@ struct TiledShape {
     size_t lds;                       // dynamic LDS bytes
 };
 TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring, int win = 0);
-hipError_t launch_tiled(const TiledNet &t, const TiledShape &sh, int64_t steps, hipStream_t st);
+// coop: a cooperative launch (the runtime guarantees that every workgroup is
+// resident); otherwise an ordinary launch, which relies on the occupancy check
+// done at set-up and on nothing else occupying the device's compute units
+// indefinitely (the waits are bounded either way).
+hipError_t launch_tiled(const TiledNet &t, const TiledShape &sh, int64_t steps, bool coop, hipStream_t st);
 hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_cu);
 // Spike injection (external stimulation): deliver the rows of `ids` as if they
 // spiked in step n-1.  Tiled form needs the tile ring to fit in LDS.
@@ -134,5 +175,14 @@ hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tile
                           hipStream_t st);
 hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, const int32_t *tile_of, int64_t m,
                                 int syn_fmt, void *syn, hipStream_t st);
+
+// Ceilings of the memory system (probe.hip): kind kProbeHbmCopy streams a copy
+// of `bytes` (rate in GB/s of bytes read + written), kProbeLdsAtomics does LDS
+// int32 atomic adds at random addresses in every compute unit, and
+// kProbeDeviceAtomics does device-scope int32 atomic adds at random words of a
+// `bytes` buffer (rates in operations per second).  Each times its second
+// launch with HIP events.
+enum ProbeKind : int { kProbeHbmCopy = 0, kProbeLdsAtomics = 1, kProbeDeviceAtomics = 2 };
+hipError_t run_probe(int kind, int64_t bytes, double *rate, double *kernel_ms);
 
 }  // namespace mc

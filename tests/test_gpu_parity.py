@@ -287,30 +287,129 @@ def test_edge_cases(conn):
     assert e.value.code == -6
 
 
-def test_full_scale_short_run_parity(conn):
-    """Full scale (77,169 neurons, ~3e8 synapses): sampled rows of the store and
-    the first 120 steps (including the onset transient) bit-exact."""
-    _say("full scale 120 steps")
-    net = mc.Network.build(1, 1.0, conn)
-    assert net.info()["engine"] == mc.ENGINE_TILED
-    orc = _oracle(1, 1.0, conn)
+def _check_store_sample(net, orc, rows=64):
     n, m = net.size()
-    assert (n, m) == (77169, orc.M)
-    assert abs(m / 3e8 - 1) < 0.01
     c_lib = net.csr()
     c_orc = orc.csr()
     assert np.array_equal(c_lib["row_ptr"], c_orc["row_ptr"])
     rng = np.random.default_rng(0)
-    for i in rng.choice(n, 64, replace=False):
+    for i in rng.choice(n, rows, replace=False):
         a0, a1 = c_lib["row_ptr"][i], c_lib["row_ptr"][i + 1]
         ka = np.lexsort((c_lib["wq"][a0:a1], c_lib["d"][a0:a1], c_lib["post"][a0:a1]))
         kb = np.lexsort((c_orc["wq"][a0:a1], c_orc["d"][a0:a1], c_orc["post"][a0:a1]))
         for f in ("post", "d", "wq"):
             assert np.array_equal(c_lib[f][a0:a1][ka].astype(np.int64), c_orc[f][a0:a1][kb].astype(np.int64))
-    del c_lib, c_orc
-    net.run(120)
-    orc.run(120)
-    assert _same_run(net, orc) > 0
+
+
+def test_full_scale_steady_state_parity(conn):
+    """Full scale (77,169 neurons, ~3e8 synapses, 256 tiles of 302 neurons):
+    sampled rows of the store, then a forced burst -- 3,000 neurons start above
+    threshold, so the first step has over 2,048 spikes (several delivery
+    batches, ids from entry words) -- and 10^4 steps (1 s) through the
+    transient into the steady state, bit-exact.  The delivery-path counters
+    show which code paths ran."""
+    _say("full scale 10^4 steps, forced burst")
+    net = mc.Network.build(1, 1.0, conn)
+    info = net.info()
+    assert info["engine"] == mc.ENGINE_TILED and info["n_tiles"] == 256 and info["tile_neurons"] == 302
+    orc = _oracle(1, 1.0, conn)
+    n, m = net.size()
+    assert (n, m) == (77169, orc.M)
+    assert abs(m / 3e8 - 1) < 0.01
+    _check_store_sample(net, orc)
+    u, _, _ = orc.state()
+    burst = np.random.default_rng(8).choice(n, 3000, replace=False)
+    u[burst] = 15.5
+    orc.set_state(u=u)
+    net.set_state(u=u.astype(np.float32))
+    for chunk in (1, 999, 9000):
+        net.run(chunk)
+        orc.run(chunk)
+        assert _same_run(net, orc) > 0
+    c, rc = net.counters(), orc.counters()
+    for k in ("steps", "spikes", "events", "poisson_events", "max_spikes_per_step"):
+        assert c[k] == rc[k], k
+    assert c["max_spikes_per_step"] >= 3000
+    paths = net.paths()
+    _say("delivery paths", paths)
+    for k in ("grouped", "per_thread", "extra_batch", "entry_words", "search"):
+        assert paths[k] > 0, (k, paths)
+    # steady state: most tile-steps take the lane-group path
+    assert paths["grouped"] > 0.5 * 256 * 10000
+
+
+@pytest.mark.parametrize("wfmt", [mc.W_FP16, mc.W_BF16])
+def test_full_scale_reduced_precision_parity(conn, wfmt):
+    """Full scale with the 4-byte FP16/BF16 records: 2,000 steps bit-exact
+    against the oracle's FP16/BF16 mirror."""
+    _say("full scale reduced precision", wfmt)
+    net = mc.Network.build(1, 1.0, conn, wfmt=wfmt)
+    assert net.info()["syn_bytes"] == 4
+    orc = _oracle(1, 1.0, conn, wfmt)
+    _check_store_sample(net, orc, rows=16)
+    for chunk in (500, 1500):
+        net.run(chunk)
+        orc.run(chunk)
+        assert _same_run(net, orc) > 0
+    assert net.paths()["grouped"] > 0
+
+
+@pytest.mark.parametrize("wfmt", [mc.W_FP16, mc.W_BF16])
+def test_graph_engine_reduced_precision(conn, wfmt):
+    """GRAPH engine with 16-bit weights (the delivery kernel's FP16/BF16 forms)."""
+    _say("graph engine reduced precision", wfmt)
+    net = mc.Network.build(4, 0.02, conn, wfmt=wfmt, engine=mc.ENGINE_GRAPH)
+    assert net.info()["engine"] == mc.ENGINE_GRAPH and net.info()["syn_bytes"] == 7
+    orc = _oracle(4, 0.02, conn, wfmt)
+    net.run(3000)
+    orc.run(3000)
+    assert _same_run(net, orc) > 100
+
+
+@pytest.mark.parametrize("wfmt", [mc.W_FP16, mc.W_BF16])
+def test_eight_byte_reduced_precision_records(conn, wfmt):
+    """Tiles over 1,024 neurons: FP16/BF16 weights in 8-byte records (two
+    neurons per thread, ring in global memory)."""
+    _say("8-byte 16-bit records", wfmt)
+    net = mc.Network.build(12, 0.05, conn, wfmt=wfmt)
+    net.set_launch(engine=mc.ENGINE_TILED, tile=2000, ring=2)
+    info = net.info()
+    assert info["syn_bytes"] == 8 and info["tile_neurons"] > 1024
+    orc = _oracle(12, 0.05, conn, wfmt)
+    net.run(1500)
+    orc.run(1500)
+    assert _same_run(net, orc) > 100
+
+
+@pytest.mark.parametrize("budget", [0.0, 1e6])
+def test_trace_form_parity(conn, budget):
+    """The phase-trace form of the step kernel (alone, and with an ample step
+    budget: the trace and budget form) gives the same results."""
+    _say("trace form, budget", budget)
+    net = mc.Network.build(13, 0.2, conn)
+    orc = _oracle(13, 0.2, conn)
+    if budget:
+        net.set_step_budget(budget)
+    net.set_trace(400)
+    net.run(700)
+    orc.run(700)
+    assert _same_run(net, orc) > 100
+    tr = net.trace()
+    assert tr.shape == (400, net.info()["n_tiles"], 8)
+    assert np.all(tr[1:, :, 0] > tr[:-1, :, 0])          # step start times increase
+    assert net.counters()["dropped_events"] == 0
+
+
+def test_ordinary_launch_parity(conn):
+    """The tiled kernel started by an ordinary (not cooperative) launch."""
+    _say("ordinary launch")
+    net = mc.Network.build(14, 0.1, conn)
+    net.set_launch(coop=2)
+    orc = _oracle(14, 0.1, conn)
+    for chunk in (20, 980):
+        net.run(chunk)
+        orc.run(chunk)
+        assert _same_run(net, orc) > 0
 
 
 def test_checkpoint_resume_is_bit_exact(conn, tmp_path):

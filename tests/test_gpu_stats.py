@@ -1,22 +1,18 @@
-"""Statistical accuracy of the reduced-precision and plain forms against the
-oracle's FP64 mode (same network, seed 1, full scale, 10 s, first 1 s
-discarded): per-population firing rate, CV of the inter-spike interval and
-binned-count correlation (Sec. 4b of Rhodes et al., arXiv 1909.08665).
+"""Statistical accuracy of the plain and reduced-precision forms against the
+oracle's FP64 mode (Sec. 4b of Rhodes et al., arXiv 1909.08665: per-population
+firing rate, CV of the inter-spike interval and binned-count correlation;
+Sec. 2a: 10 s of biological time with the first 1 s discarded).
 
-Chaotic dynamics make FP32 and FP64 runs diverge spike by spike once a
-rounding difference flips one threshold decision, so the comparison is
-statistical.  tests/golden/fp64_stats_full.json (written by
-tests/golden/make_fp64_stats.py from the oracle alone) holds the FP64 run with
-the model's background stream and four FP64 runs that differ from it only by
-one neuron forced to spike in the first step -- the smallest discrete change
-of a run.  Their largest deviation from the reference is the noise floor of a
-run with the same background input; the FP32 store must stay within
-max(2 %, 2 x floor) of the FP64 rate and max(5 %, 2 x floor) of its CV-ISI.
-The FP16/BF16 stores perturb every weight by up to 2^-11 / 2^-8 relative; on
-the stand-in network that acts like a different network realisation and can
-move a population's operating point well beyond that floor, so for them the
-per-population errors are reported and only the whole-network rate is bounded
-(within 30 %).
+Chaotic dynamics make an FP32 run and an FP64 run diverge spike by spike once a
+rounding difference flips one threshold decision, so the forms are compared as
+ensembles of equally valid runs: tests/golden/fp64_ensemble_full.json (written
+by tests/golden/make_fp64_stats.py from the oracle alone) holds eight FP64 runs
+of the full-scale network (seed 1), run k starting with neuron (7919 k) mod N
+above threshold; the GPU repeats the same eight starts for each weight store
+(FP32, FP16, BF16).  The acceptance bar is fixed in advance and the same for
+every population: the ensemble-mean rate within 2 % and the ensemble-mean
+CV-ISI within 5 % of the FP64 ensemble mean.  The correlation coefficient is
+reported, not bounded.
 """
 import json
 import os
@@ -30,48 +26,60 @@ from synth_inputs import FULL_SIZE, standin_conn_table
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp64_stats_full.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp64_ensemble_full.json")
 STEPS, DISCARD = 100000, 10000
+ENSEMBLE = 8
+RATE_TOL, CV_TOL = 0.02, 0.05          # the bar: 2 % on rate, 5 % on CV-ISI, every population
 
 
-def _fp64_reference():
+def _ensemble_table(runs):
+    rate = np.array([[r[p]["rate_hz"] for p in POP_NAMES] for r in runs])
+    cv = np.array([[r[p]["cv_isi"] for p in POP_NAMES] for r in runs])
+    corr = np.array([[r[p]["corr"] for p in POP_NAMES] for r in runs])
+    return rate, cv, corr
+
+
+@pytest.fixture(scope="module")
+def fp64():
     data = json.load(open(GOLDEN))
-    base = data["1"]["stats"]
-    pert = [data[k]["stats"] for k in ("1/perturb1", "1/perturb2", "1/perturb3", "1/perturb4") if k in data]
-    assert len(pert) >= 2, "golden FP64 statistics missing"
-    ref = {}
-    for p in POP_NAMES:
-        r0, c0 = base[p]["rate_hz"], base[p]["cv_isi"]
-        fr = max(abs(x[p]["rate_hz"] - r0) / r0 for x in pert)
-        fc = max(abs(x[p]["cv_isi"] - c0) / c0 for x in pert)
-        ref[p] = dict(rate=r0, rate_tol=max(0.02, 2 * fr), cv=c0, cv_tol=max(0.05, 2 * fc))
-    return ref
+    runs = [data[f"perturb{k}"]["stats"] for k in range(1, ENSEMBLE + 1)]
+    for k in range(1, ENSEMBLE + 1):
+        assert data[f"perturb{k}"]["steps"] == STEPS and data[f"perturb{k}"]["discard"] == DISCARD
+    return _ensemble_table(runs)
 
 
 @pytest.mark.parametrize("wfmt", [mc.W_FP32, mc.W_FP16, mc.W_BF16])
-def test_statistics_against_fp64(wfmt):
-    ref = _fp64_reference()
-    print(f"[case] stats wfmt={wfmt}", flush=True)
+def test_ensemble_statistics_against_fp64(wfmt, fp64, tmp_path):
+    name = {mc.W_FP32: "FP32", mc.W_FP16: "FP16", mc.W_BF16: "BF16"}[wfmt]
+    print(f"[case] ensemble statistics {name}", flush=True)
     net = mc.Network.build(1, 1.0, standin_conn_table(), wfmt=wfmt)
-    net.run(STEPS)
-    st, ids = net.spikes()
+    start = str(tmp_path / "start.ckpt")
+    net.save(start)
+    u0, _, _ = net.state()
     off = np.concatenate([[0], np.cumsum(FULL_SIZE)])
-    got = population_stats(st, ids, off, DISCARD, STEPS)
-    strict = []
-    for p in POP_NAMES:
-        r, c = got[p]["rate_hz"], got[p]["cv_isi"]
-        er = abs(r - ref[p]["rate"]) / ref[p]["rate"]
-        ec = abs(c - ref[p]["cv"]) / ref[p]["cv"]
-        print(f"  {p:5s} rate {r:8.3f} Hz (FP64 {ref[p]['rate']:8.3f}, err {er:6.2%}, tol {ref[p]['rate_tol']:6.2%})"
-              f"  CV {c:6.3f} (FP64 {ref[p]['cv']:6.3f}, err {ec:6.2%}, tol {ref[p]['cv_tol']:6.2%})"
-              f"  corr {got[p]['corr']:.4f}", flush=True)
-        if wfmt == mc.W_FP32:
-            assert er <= ref[p]["rate_tol"], (p, r, ref[p]["rate"])
-            assert ec <= ref[p]["cv_tol"], (p, c, ref[p]["cv"])
-        strict.append(er <= 0.02 and ec <= 0.05)
-    print(f"  populations within 2 % rate and 5 % CV: {sum(strict)} of 8", flush=True)
-    sizes = np.diff(off)
-    total = sum(got[p]["rate_hz"] * n for p, n in zip(POP_NAMES, sizes))
-    total64 = sum(ref[p]["rate"] * n for p, n in zip(POP_NAMES, sizes))
-    print(f"  whole-network rate {total / sizes.sum():.3f} Hz (FP64 {total64 / sizes.sum():.3f})", flush=True)
-    assert abs(total / total64 - 1) < 0.3
+    runs = []
+    for k in range(1, ENSEMBLE + 1):
+        net.load(start)
+        u = u0.copy()
+        u[(7919 * k) % len(u)] = 16.0                 # theta + 1 mV: spikes in the first step
+        net.set_state(u=u)
+        net.run(STEPS)
+        st, ids = net.spikes()
+        runs.append(population_stats(st, ids, off, DISCARD, STEPS))
+        print(f"  run {k}: {len(st)} spikes", flush=True)
+    rate, cv, corr = _ensemble_table(runs)
+    r64, c64, k64 = fp64
+    bad = []
+    for a, p in enumerate(POP_NAMES):
+        mr, m64 = rate[:, a].mean(), r64[:, a].mean()
+        mc_, mc64 = cv[:, a].mean(), c64[:, a].mean()
+        er, ec = abs(mr - m64) / m64, abs(mc_ - mc64) / mc64
+        # spread of the FP64 ensemble mean (standard error), for the record
+        se_r = r64[:, a].std(ddof=1) / np.sqrt(ENSEMBLE) / m64
+        se_c = c64[:, a].std(ddof=1) / np.sqrt(ENSEMBLE) / mc64
+        print(f"  {p:5s} rate {mr:7.4f} Hz vs FP64 {m64:7.4f} (err {er:6.2%}, FP64 s.e. {se_r:6.3%})  "
+              f"CV {mc_:6.4f} vs {mc64:6.4f} (err {ec:6.2%}, s.e. {se_c:6.3%})  "
+              f"corr {corr[:, a].mean():.5f} vs {k64[:, a].mean():.5f}", flush=True)
+        if er > RATE_TOL or ec > CV_TOL:
+            bad.append((p, er, ec))
+    assert not bad, bad
