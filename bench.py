@@ -25,14 +25,14 @@ DT_S = 1e-4
 HBM_PEAK_GBS = 8000.0
 METRIC = "real-time factor + synaptic events/s, full 77k-neuron microcircuit, 1 GPU"
 WFMT = {"fp32": 0, "fp16": 1, "bf16": 2}
-INIT_MODES = {"uniform": 0, "zero": 1}
+INIT_MODES = {"uniform": 0, "zero": 1, "relaxed": 2}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None, single_steps=0):
+def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None, single_steps=0, init_kw=None):
     """The oracle (FP32 mirror) on this host's cores, on a bounded sample of the
     same workload: same network, `steps` steps after `warm` untimed steps on
     every core, then (single_steps > 0) the next single_steps on one thread."""
@@ -40,7 +40,8 @@ def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None, single_steps=0):
 
     cores = O.max_threads()
     t = time.time()
-    params = O.default_params() if i_dc is None else O.default_params(poisson_on=False, i_dc=i_dc)
+    kw = dict(init_kw or {})
+    params = O.default_params(**kw) if i_dc is None else O.default_params(poisson_on=False, i_dc=i_dc, **kw)
     net = O.OracleNet.build(seed, scale, conn.reshape(64), params)
     log(f"oracle build {time.time() - t:.1f}s ({cores} threads)")
     net.run(warm)
@@ -77,9 +78,16 @@ PHASES = (("update+publish", 0, 1), ("wait for all tiles", 3, 4),
 def step_latency(net):
     """Per-step timing of the tiled kernel from its 100 MHz phase timestamps:
     phase means and the step period against the 100 us real-time deadline."""
-    tr = net.trace().astype(np.int64)                 # [steps, tiles, 8]
+    tr, launch = net.trace(launch=True)               # [steps, tiles, 8], [tiles, 4]
+    tr = tr.astype(np.int64)
     if tr.shape[0] < 2:
         return None
+    launch = launch.astype(np.int64)
+    prologue = (launch[:, 1] - launch[:, 0]) * 0.01                       # us per tile
+    epilogue = (launch[:, 3] - launch[:, 2]) * 0.01
+    skew = (launch[:, 0].max() - launch[:, 0].min()) * 0.01
+    log(f"  launch: prologue max {prologue.max():.2f} us, epilogue max {epilogue.max():.2f} us, "
+        f"start skew over tiles {skew:.2f} us")
     tr[:, :, 5] = np.where(tr[:, :, 5] == 0, tr[:, :, 4], tr[:, :, 5])   # steps without spikes
     per = np.diff(tr[:, :, 0], axis=0).max(axis=1) * 0.01                # us, slowest tile
     phases = {}
@@ -92,7 +100,9 @@ def step_latency(net):
     return {"steps": int(tr.shape[0] - 1), "mean_us": round(float(per.mean()), 3),
             "p50_us": round(float(np.median(per)), 3), "p99_us": round(float(np.percentile(per, 99)), 3),
             "max_us": round(float(per.max()), 3), "deadline_us": 100.0,
-            "frac_over_deadline": float((per > 100.0).mean()), "phases_us": phases}
+            "frac_over_deadline": float((per > 100.0).mean()), "phases_us": phases,
+            "launch_us": {"prologue_max": round(float(prologue.max()), 3), "epilogue_max": round(float(epilogue.max()), 3),
+                          "start_skew": round(float(skew), 3)}}
 
 
 # Workloads: (seeds, scales, default weight format, description)
@@ -252,8 +262,9 @@ def main():
     ap.add_argument("--engine", choices=["auto", "graph", "tiled"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
-    ap.add_argument("--init", choices=sorted(INIT_MODES), default="uniform",
-                    help="initial membrane potentials: uniform in [0, theta) (default) or all at rest")
+    ap.add_argument("--init", choices=sorted(INIT_MODES), default="relaxed",
+                    help="initial state: relaxed (default; per-population steady-state moments of u and I, "
+                         "as the paper starts from a relaxed state), uniform u in [0, theta), or all at rest")
     ap.add_argument("--device-build", action="store_true", help="draw and sort the synapse store on the GPU")
     ap.add_argument("--dc", action="store_true",
                     help="DC-input workload: no Poisson background, each population driven by the mean "
@@ -287,7 +298,7 @@ def main():
     import torch
 
     import paper_1909_08665_amd as mc
-    from synth_inputs import dc_standin_amplitudes, standin_conn_table, standin_description
+    from synth_inputs import dc_standin_amplitudes, relaxed_start, standin_conn_table, standin_description
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -311,7 +322,7 @@ def main():
     t = time.time()
     db = int(args.device_build)
     drive = dict(poisson_on=False, i_dc=dc_standin_amplitudes()) if args.dc else {}
-    drive["init_mode"] = INIT_MODES[args.init]
+    drive.update(relaxed_start() if args.init == "relaxed" else {"init_mode": INIT_MODES[args.init]})
     if n_inst == 1:
         net = mc.Network.build(seeds[0], scales[0], conn, wfmt=WFMT[args.wfmt], engine=engine, device_build=db, **drive)
     else:
@@ -458,7 +469,8 @@ def main():
     if not args.no_cpu_baseline:
         # one instance of the workload (the first) on the host cores, scaled to the batch
         cb = cpu_baseline(seeds[0], scales[0], conn, args.cpu_warm, args.cpu_steps,
-                          i_dc=dc_standin_amplitudes() if args.dc else None, single_steps=args.cpu_single_steps)
+                          i_dc=dc_standin_amplitudes() if args.dc else None, single_steps=args.cpu_single_steps,
+                          init_kw={k: v for k, v in drive.items() if k.startswith("init_")})
         if n_inst > 1:
             cb["sample"] += f"; instance 0 of {n_inst} (per-instance rate)"
         out["cpu_baseline"] = cb

@@ -77,7 +77,8 @@ typedef struct mc_config {
                                     connected; each in [0, 1).  Required. */
     int32_t wfmt;                /* MC_W_FP32 | MC_W_FP16 | MC_W_BF16 */
     int32_t poisson_on;          /* 1: Poisson background drive (default); 0: none */
-    int32_t init_mode;           /* 0: u ~ U[0, theta) (default); 1: u = 0 */
+    int32_t init_mode;           /* 0: u ~ U[0, theta), I = 0 (default); 1: u = I = 0;
+                                    2: relaxed start (init_u_*, init_i_* below) */
     int32_t engine;              /* MC_ENGINE_* */
     int64_t record_capacity;     /* device recorder entries; 0 = automatic */
     double full_size[MC_NPOP];   /* full-scale population sizes */
@@ -103,6 +104,14 @@ typedef struct mc_config {
                                     can differ from the host build's only when its exact
                                     value lies within ~1e-13 of a rounding boundary).
                                     Needs fewer than 2^24 neurons and 2^32 synapses. */
+    /* Relaxed start (init_mode 2; Sec. 4a: initial potentials chosen so that the first
+       steps already look like the steady state).  Per population: the synaptic current
+       I ~ N(init_i_mean_pa, init_i_sd_pa); the potential u from the density of
+       N(init_u_mean_mv, init_u_sd_mv) minus its mirror image in the threshold
+       (zero at theta, like the steady state's), drawn by rejection from Philox blocks
+       (neuron, 1 + attempt, 0, 3).  Needs init_u_sd_mv > 0, init_u_mean_mv < theta. */
+    double init_u_mean_mv[MC_NPOP], init_u_sd_mv[MC_NPOP];
+    double init_i_mean_pa[MC_NPOP], init_i_sd_pa[MC_NPOP];
 } mc_config;
 
 typedef struct mc_counters {
@@ -154,9 +163,14 @@ typedef struct mc_launch {
                                     tiles' words, in units of 64 clocks, 1..255; -1 for none.
                                     Speed only: results do not depend on it. */
     int32_t coop;                /* TILED engine: 1 cooperative launch (the runtime guarantees
-                                    that all workgroups are resident at once; the default),
-                                    2 ordinary launch (relies on the occupancy check made at
-                                    set-up).  Speed only. */
+                                    that all workgroups are resident at once), 2 ordinary
+                                    launch (the default: 15-20 us cheaper per launch; relies on
+                                    the occupancy check made at set-up, and on no other work
+                                    holding the compute units for longer than the wait limit
+                                    of mc_set_wait_limit).  Speed only. */
+    int32_t lanes;               /* TILED engine: lanes per spike when a step's (or an injection's)
+                                    spikes are delivered by a cursor, 1..64 (default: about the
+                                    mean sub-row length).  Speed only. */
 } mc_launch;
 
 /* Fill *cfg with the defaults of Sec. 2a; conn_probs is left NULL. */
@@ -307,9 +321,12 @@ int mc_get_timing(struct mc_net *net, double *kernel_ms, int64_t *launches);
  * mc_set_trace(net, k) records, for the first k steps of the next mc_run, eight
  * words per (step, tile) from the GPU's constant 100 MHz clock: step start,
  * spikes published, barrier arrival, next Poisson draw done, barrier passed,
- * spike counts gathered, delivery done, and the step's spike count.  k = 0
- * disables it.  mc_get_trace copies [k][n_tiles][8] words into `out` (cap
- * entries) and sets *count; MC_ERR_BUFFER_TOO_SMALL if cap is too small.
+ * spike counts gathered, delivery done, and the step's spike count; then one
+ * more row per tile with the launch's own timestamps: kernel entry, start of
+ * the first step (after the ring and state are loaded), end of the last step,
+ * and the end of the write-back.  k = 0 disables it.  mc_get_trace copies
+ * [k + 1][n_tiles][8] words into `out` (cap entries) and sets *count;
+ * MC_ERR_BUFFER_TOO_SMALL if cap is too small.
  */
 int mc_set_trace(struct mc_net *net, int32_t steps);
 int mc_get_trace(struct mc_net *net, uint64_t *out, int64_t cap, int64_t *count);

@@ -70,7 +70,7 @@ class BruteNet:
     """Explicit network: pop_sizes[8], synapse lists (pre, post, w pA, d steps)."""
 
     def __init__(self, pop_sizes, pre, post, w, d, *, seed=1, fp64=False, wfmt=0, poisson_on=True,
-                 init_zero=False, i_dc=None, k_ext=None, full_params=None):
+                 init_zero=False, i_dc=None, k_ext=None, full_params=None, relaxed=None):
         p = dict(nu_bg=8.0, dt=0.1, tau_m=10.0, c_m=250.0, tau_s=0.5, t_ref=2.0, theta=15.0, w_ext=87.8)
         if full_params:
             p.update(full_params)
@@ -114,13 +114,40 @@ class BruteNet:
         f32 = np.float32
         self.u, self.I = [], []
         for i in range(self.N):
-            u0 = 0.0 if init_zero else p["theta"] * ((philox4x64_10((i, 0, 0, 3), (self.seed, 0))[0] >> 11) * 2.0 ** -53)
+            i0 = 0.0
+            if relaxed is not None:
+                u0, i0 = self._relaxed(i, self.pop_of[i], relaxed)
+            elif init_zero:
+                u0 = 0.0
+            else:
+                u0 = p["theta"] * ((philox4x64_10((i, 0, 0, 3), (self.seed, 0))[0] >> 11) * 2.0 ** -53)
             self.u.append(u0 if fp64 else f32(u0))
-            self.I.append(0.0 if fp64 else f32(0.0))
+            self.I.append(i0 if fp64 else f32(i0))
         self.refr = [0] * self.N
         self.ring = [[0.0 if fp64 else 0 for _ in range(self.N)] for _ in range(R)]
         self.step = 0
         self.spikes = []
+
+    def _relaxed(self, i, a, r):
+        """Relaxed start: I ~ N(i_mean, i_sd) from the first normal pair's second
+        member; u ~ N(u_mean, u_sd) restricted to u < theta with acceptance
+        1 - exp(-2 (theta - u)(theta - u_mean) / u_sd^2) (the normal density minus
+        its image in the threshold), trying blocks (i, 1 + k, 0, 3) in turn."""
+        mu, sd, th = r["u_mean"][a], r["u_sd"][a], self.p["theta"]
+        two_pi = 6.283185307179586
+        cur = 0.0
+        for k in range(64):
+            x = philox4x64_10((i, 1 + k, 0, 3), (self.seed, 0))
+            rad = math.sqrt(-2.0 * math.log(((x[0] >> 11) + 1) * 2.0 ** -53))
+            phi = two_pi * ((x[1] >> 11) * 2.0 ** -53)
+            z1 = rad * math.cos(phi)
+            if k == 0:
+                cur = r["i_mean"][a] + r["i_sd"][a] * (rad * math.sin(phi))
+            v = mu + sd * z1
+            accept = 1.0 - math.exp(-2.0 * (th - v) * (th - mu) / (sd * sd))
+            if v < th and (x[2] >> 11) * 2.0 ** -53 < accept:
+                return v, cur
+        return 0.0, cur
 
     def poisson(self, n, i):
         """Count for neuron i at step n: 32-bit half i mod 8 of the block

@@ -40,7 +40,12 @@
  *   R7 Background weight is 87.8 pA, fixed; background spikes enter I in the step
  *      they are drawn.  Count ~ Poisson(8 Hz * K_ext * dt) by integer inversion of
  *      a 32-bit uniform against K_MAX fixed-point CDF thresholds.
- *   R8 Initial state: u ~ U[0, theta), I = 0, not refractory.
+ *   R8 Initial state: u ~ U[0, theta), I = 0, not refractory (init_mode 0), or all zero
+ *      (1), or a relaxed start (2; Sec. 4a: initial potentials chosen so that the
+ *      first steps look like the steady state, values not given): per population
+ *      I ~ N(mu_I, sd_I) and u drawn from the density of N(mu_u, sd_u) with an
+ *      absorbing threshold, phi((u-mu)/sd) - phi((u-(2 theta-mu))/sd) for u < theta
+ *      (the method of images), by rejection; the moments are inputs.
  *   R9 Random numbers: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
  *      counter (c0, c1, c2, tag) -- one block per synapse and per neuron initial
  *      value; one block per step and group of 8 consecutive neurons for the
@@ -146,6 +151,8 @@ typedef struct {
     uint64_t pois_stream;    /* second key word of the Poisson draws: 0 for the model; other
                                 values give independent background realisations on the same
                                 network (noise-floor estimates only) */
+    double init_u_mean_mv[OR_NPOP], init_u_sd_mv[OR_NPOP];   /* relaxed start (init_mode 2) */
+    double init_i_mean_pa[OR_NPOP], init_i_sd_pa[OR_NPOP];
 } or_params;
 
 typedef struct {
@@ -257,6 +264,33 @@ static void compute_constants(or_net *nt)
     }
 }
 
+/* Relaxed initial state of neuron i (instance-local index) of population a
+   (reading R8, init_mode 2).  Block (i, 1 + r, 0, TAG_INIT) gives the normal
+   pair (z1, z2) by Box-Muller on its words 0 and 1 and a uniform in word 2:
+   I takes mu_I + sd_I z2 of the first block; u takes mu_u + sd_u z1 of the first
+   block r whose value lies below theta and whose uniform is below the image
+   density's acceptance ratio 1 - exp(-2 (theta - u)(theta - mu_u) / sd_u^2). */
+static void relaxed_state(const or_net *nt, int32_t i, int a, double *u, double *I)
+{
+    const double mu = nt->p.init_u_mean_mv[a], sd = nt->p.init_u_sd_mv[a], th = nt->theta;
+    const double two_pi = 6.283185307179586;
+    *u = 0.0;
+    for (int r = 0; r < 64; ++r) {
+        uint64_t c[4] = {(uint64_t)i, (uint64_t)(1 + r), 0, TAG_INIT}, k[2] = {nt->seed, 0}, x[4];
+        or_philox(c, k, x);
+        const double rad = sqrt(-2.0 * log(u53p(x[0])));
+        const double phi = two_pi * u53(x[1]);
+        const double z1 = rad * cos(phi);
+        if (r == 0) *I = nt->p.init_i_mean_pa[a] + nt->p.init_i_sd_pa[a] * (rad * sin(phi));
+        const double v = mu + sd * z1;
+        const double accept = 1.0 - exp(-2.0 * (th - v) * (th - mu) / (sd * sd));
+        if (v < th && u53(x[2]) < accept) {
+            *u = v;
+            return;
+        }
+    }
+}
+
 /* Counting sort of the synapse list by presynaptic neuron (stable), then the
    ring depth, the int32 bound and the initial state. */
 static int finish_network(or_net *nt, int32_t *pre, int32_t *post, int32_t *wq,
@@ -330,13 +364,21 @@ static int finish_network(or_net *nt, int32_t *pre, int32_t *post, int32_t *wq,
         if (!nt->ud || !nt->Id || !nt->ringd) { set_err("out of host memory"); return -1; }
     }
     for (int32_t i = 0; i < N; ++i) {
-        double u0 = 0.0;
+        double u0 = 0.0, i0 = 0.0;
         if (nt->p.init_mode == 0) {
             uint64_t c[4] = {(uint64_t)i, 0, 0, TAG_INIT}, k[2] = {nt->seed, 0}, x[4];
             or_philox(c, k, x);
             u0 = nt->theta * u53(x[0]);
+        } else if (nt->p.init_mode == 2) {
+            relaxed_state(nt, i, nt->pop_of[i], &u0, &i0);
         }
-        if (nt->p.mode == 0) nt->uf[i] = (float)u0; else nt->ud[i] = u0;
+        if (nt->p.mode == 0) {
+            nt->uf[i] = (float)u0;
+            nt->If[i] = (float)i0;
+        } else {
+            nt->ud[i] = u0;
+            nt->Id[i] = i0;
+        }
     }
     return 0;
 }
@@ -358,6 +400,13 @@ static int check_params(const or_params *p)
         set_err("time constants, capacitance and dt must be positive"); return -1;
     }
     if (p->tau_m_ms == p->tau_syn_ms) { set_err("tau_m must differ from tau_syn"); return -1; }
+    if (p->init_mode < 0 || p->init_mode > 2) { set_err("init_mode must be 0, 1 or 2"); return -1; }
+    if (p->init_mode == 2)
+        for (int a = 0; a < OR_NPOP; ++a)
+            if (!(p->init_u_sd_mv[a] > 0.0) || !(p->init_u_mean_mv[a] < p->theta_mv) || !(p->init_i_sd_pa[a] >= 0.0)) {
+                set_err("relaxed start needs sd_u > 0, mean_u < theta and sd_I >= 0 for every population");
+                return -1;
+            }
     return 0;
 }
 

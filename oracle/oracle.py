@@ -45,6 +45,8 @@ class OrParams(C.Structure):
         ("d_mean_exc_ms", C.c_double), ("d_sd_exc_ms", C.c_double),
         ("d_mean_inh_ms", C.c_double), ("d_sd_inh_ms", C.c_double),
         ("pois_stream", C.c_uint64),
+        ("init_u_mean_mv", C.c_double * NPOP), ("init_u_sd_mv", C.c_double * NPOP),
+        ("init_i_mean_pa", C.c_double * NPOP), ("init_i_sd_pa", C.c_double * NPOP),
     ]
 
 
@@ -63,7 +65,10 @@ def default_params(mode=MIRROR, wfmt=W_FP32, poisson_on=True, init_mode=0, i_dc=
     p.d_mean_exc_ms, p.d_sd_exc_ms, p.d_mean_inh_ms, p.d_sd_inh_ms = 1.5, 0.75, 0.8, 0.4
     p.pois_stream = 0
     for k, v in over.items():
-        setattr(p, k, v)
+        if k.startswith("init_") and k != "init_mode":
+            getattr(p, k)[:] = [float(x) for x in v]
+        else:
+            setattr(p, k, v)
     return p
 
 

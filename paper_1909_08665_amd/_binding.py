@@ -38,6 +38,8 @@ class McConfig(C.Structure):
         ("d_mean_exc_ms", C.c_double), ("d_sd_exc_ms", C.c_double),
         ("d_mean_inh_ms", C.c_double), ("d_sd_inh_ms", C.c_double),
         ("device_build", C.c_int32),
+        ("init_u_mean_mv", C.c_double * NPOP), ("init_u_sd_mv", C.c_double * NPOP),
+        ("init_i_mean_pa", C.c_double * NPOP), ("init_i_sd_pa", C.c_double * NPOP),
     ]
 
 
@@ -56,7 +58,7 @@ class McInfo(C.Structure):
 
 class McLaunch(C.Structure):
     _fields_ = [("engine", C.c_int32), ("tile", C.c_int32), ("ring", C.c_int32), ("graph_chunk", C.c_int32), ("seg", C.c_int32), ("block", C.c_int32),
-                ("deliver_grid", C.c_int32), ("poll_delay", C.c_int32), ("coop", C.c_int32)]
+                ("deliver_grid", C.c_int32), ("poll_delay", C.c_int32), ("coop", C.c_int32), ("lanes", C.c_int32)]
 
 
 # Every entry point declared in include/mc.h.
@@ -154,7 +156,7 @@ def make_config(conn, *, wfmt=W_FP32, poisson_on=True, init_mode=0, engine=ENGIN
     if i_dc is not None:
         cfg.i_dc_pa[:] = [float(x) for x in i_dc]
     for k, v in params.items():
-        if k in ("full_size", "k_ext"):
+        if k in ("full_size", "k_ext", "init_u_mean_mv", "init_u_sd_mv", "init_i_mean_pa", "init_i_sd_pa"):
             getattr(cfg, k)[:] = [float(x) for x in v]
         else:
             setattr(cfg, k, v)
@@ -207,12 +209,13 @@ class Network:
         _check(lib().mc_run(self._h, int(steps)))
 
     def set_launch(self, engine=0, tile=0, ring=0, graph_chunk=0, seg=0, block=0, deliver_grid=0, poll_delay=0,
-                   coop=0):
+                   coop=0, lanes=0):
         """ring: 0 auto, 1 tile ring in LDS, 2 tile ring in global memory (tiled engine).
         poll_delay: tiled engine, sleep before polling in units of 64 clocks (-1 none).
         coop: tiled engine, 1 cooperative launch, 2 ordinary launch.
+        lanes: tiled engine, lanes per spike for cursor delivery (1..64).
         0 keeps the current value of any knob."""
-        l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid, poll_delay, coop)
+        l = McLaunch(engine, tile, ring, graph_chunk, seg, block, deliver_grid, poll_delay, coop, lanes)
         _check(lib().mc_set_launch(self._h, C.byref(l)))
 
     def set_step_budget(self, budget_us):
@@ -263,16 +266,19 @@ class Network:
         """Record per-step phase timestamps for the first `steps` steps of the next run."""
         _check(lib().mc_set_trace(self._h, int(steps)))
 
-    def trace(self):
+    def trace(self, launch=False):
         """[steps, tiles, 8] uint64: 100 MHz timestamps of the step phases (slot 7:
-        the step's spike count)."""
+        the step's spike count); with launch=True also the [tiles, 4] launch
+        timestamps (entry, first step, end of the last step, end of write-back)."""
         cnt = C.c_int64()
         lib().mc_get_trace(self._h, None, 0, C.byref(cnt))
         out = np.zeros(cnt.value, dtype=np.uint64)
         if cnt.value:
             _check(lib().mc_get_trace(self._h, _ptr(out), cnt.value, C.byref(cnt)))
         info = self.info()
-        return out.reshape(-1, max(1, info["n_tiles"]), 8)
+        rows = out.reshape(-1, max(1, info["n_tiles"]), 8)
+        steps = rows[:-1] if len(rows) else rows
+        return (steps, rows[-1, :, :4] if len(rows) else None) if launch else steps
 
     def save(self, path):
         _check(lib().mc_save_state(self._h, os.fsencode(path)))

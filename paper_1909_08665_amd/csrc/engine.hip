@@ -87,11 +87,15 @@ struct mc_net {
     uint64_t *work = nullptr;
     unsigned long long *pois_acc = nullptr;
     int64_t pois_slots = 0;
-    // Two spike recorders (step << 32 | id) and their pinned host copies: the
-    // tiled engine alternates them between segments and drains one while the
-    // next segment runs; the graph engine uses the first.
-    uint64_t *rec[2] = {};
-    uint64_t *h_rec[2] = {};
+    // Two spike recorders and their pinned host copies, each a 64-byte head
+    // (mc::RecHead: the counters of the tiled launch that used it) followed by
+    // the entries (step << 32 | id): the tiled engine alternates them between
+    // segments and drains one while the next segment runs, with one copy of the
+    // head and entries per launch; the graph engine uses the first's entries.
+    void *rblk[2] = {};
+    void *h_rblk[2] = {};
+    uint64_t *rec[2] = {};            // entries of rblk[b]
+    uint64_t *h_rec[2] = {};          // entries of h_rblk[b]
     int64_t rec_cap = 0;
     mc::StepCtl *h_ctl = nullptr;
     hipStream_t copy_stream = nullptr;
@@ -111,12 +115,10 @@ struct mc_net {
     int32_t syn_fmt = 0;
     uint64_t *xchg = nullptr;
     uint64_t *xent = nullptr;
-    // Per-launch counters: TiledCtl followed by the dropped-event counts
-    // [2][n_tiles]; copied whole into h_tblk[buf] after each launch.
-    void *tblk = nullptr;
-    void *h_tblk[2] = {};
+    unsigned long long *dropped = nullptr;       // [2][n_tiles] events dropped by the step budget, per buffer
+    unsigned long long *h_dropped = nullptr;     // pinned copy (copied only while a budget is set)
+    uint32_t *abort_word = nullptr;              // epoch of a launch in which a wait gave up
     unsigned long long *paths = nullptr;         // [kPaths] tile-steps per delivery path
-    size_t tblk_bytes = 0;
     uint32_t budget_ticks = 0;                   // step budget, 100 MHz ticks; 0: none
     int64_t xent_high = 0;            // entry words may carry tags of steps below this
     int64_t xchg_high = 0;            // tile words carry tags of steps below this
@@ -140,8 +142,9 @@ struct mc_net {
     int deliver_grid = 1024;
     int poll_delay = 0;
     bool poll_delay_set = false;      // chosen by mc_set_launch or the tuner; otherwise by tile count
-    bool coop = true;                 // tiled engine: cooperative launch
+    bool coop = false;                // tiled engine: cooperative launch (else ordinary)
     int lanes = 16;                   // tiled engine: lanes per spike for cursor delivery
+    bool lanes_set = false;           // chosen by mc_set_launch; otherwise from the mean sub-row length
     hipGraphExec_t graph_exec = nullptr;
     int graph_k = 0;
 
@@ -222,12 +225,11 @@ void release(mc_net *nt)
     if (nt->copy_stream) hipStreamSynchronize(nt->copy_stream);
     void *bufs[] = {nt->u, nt->cur, nt->refr, nt->meta, nt->inst_off, nt->seeds, nt->cdc, nt->pois_thr,
                     nt->ring, nt->row_ptr, nt->tgt, nt->w, nt->dly, nt->ctl, nt->work, nt->pois_acc,
-                    nt->rec[0], nt->rec[1], nt->subrow, nt->syn, nt->xchg, nt->xent, nt->tblk, nt->trace, nt->paths,
-                    nt->tiles_dev, nt->gring, nt->inject_buf};
+                    nt->rblk[0], nt->rblk[1], nt->subrow, nt->syn, nt->xchg, nt->xent, nt->dropped, nt->abort_word,
+                    nt->trace, nt->paths, nt->tiles_dev, nt->gring, nt->inject_buf};
     for (void *b : bufs)
         if (b) hipFree(b);
-    for (void *b : {static_cast<void *>(nt->h_rec[0]), static_cast<void *>(nt->h_rec[1]), static_cast<void *>(nt->h_ctl),
-                    nt->h_tblk[0], nt->h_tblk[1]})
+    for (void *b : {nt->h_rblk[0], nt->h_rblk[1], static_cast<void *>(nt->h_ctl), static_cast<void *>(nt->h_dropped)})
         if (b) hipHostFree(b);
     if (nt->ev0) hipEventDestroy(nt->ev0);
     if (nt->ev1) hipEventDestroy(nt->ev1);
@@ -273,6 +275,15 @@ int params_from_config(const mc_config *cfg, mc::ModelParams &p)
     p.wfmt = cfg->wfmt;
     p.poisson_on = cfg->poisson_on ? 1 : 0;
     p.init_mode = cfg->init_mode;
+    if (p.init_mode < 0 || p.init_mode > 2) return fail(MC_ERR_ARG, "init_mode must be 0, 1 or 2");
+    std::memcpy(p.init_u_mean, cfg->init_u_mean_mv, sizeof(p.init_u_mean));
+    std::memcpy(p.init_u_sd, cfg->init_u_sd_mv, sizeof(p.init_u_sd));
+    std::memcpy(p.init_i_mean, cfg->init_i_mean_pa, sizeof(p.init_i_mean));
+    std::memcpy(p.init_i_sd, cfg->init_i_sd_pa, sizeof(p.init_i_sd));
+    if (p.init_mode == 2)
+        for (int a = 0; a < mc::kPops; ++a)
+            if (!(p.init_u_sd[a] > 0.0) || !(p.init_u_mean[a] < cfg->theta_mv) || !(p.init_i_sd[a] >= 0.0))
+                return fail(MC_ERR_ARG, "relaxed start needs sd_u > 0, mean_u < theta and sd_I >= 0 for every population");
     const double ref = p.t_ref_ms / p.dt_ms;
     if (!(ref >= 0.0 && ref < 255.0)) return fail(MC_ERR_ARG, "refractory time must be below 255 steps");
     return MC_OK;
@@ -339,8 +350,13 @@ int upload(mc_net *nt, const mc_config *cfg, const std::vector<mc::SynSeg> *segs
     if (cap <= 0) cap = std::max<int64_t>(int64_t{1} << 22, 64 * N);
     nt->rec_cap = cap;
     for (int b = 0; b < 2; ++b) {
-        if ((rc = dalloc(&nt->rec[b], cap))) return rc;
-        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_rec[b]), cap * sizeof(uint64_t), hipHostMallocDefault));
+        const size_t bytes = sizeof(mc::RecHead) + static_cast<size_t>(cap) * sizeof(uint64_t);
+        hipError_t e = hipMalloc(&nt->rblk[b], bytes);
+        if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        HIP_TRY(hipHostMalloc(&nt->h_rblk[b], bytes, hipHostMallocDefault));
+        HIP_TRY(hipMemset(nt->rblk[b], 0, sizeof(mc::RecHead)));
+        nt->rec[b] = reinterpret_cast<uint64_t *>(static_cast<char *>(nt->rblk[b]) + sizeof(mc::RecHead));
+        nt->h_rec[b] = reinterpret_cast<uint64_t *>(static_cast<char *>(nt->h_rblk[b]) + sizeof(mc::RecHead));
     }
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl), sizeof(mc::StepCtl), hipHostMallocDefault));
 
@@ -369,7 +385,7 @@ int upload(mc_net *nt, const mc_config *cfg, const std::vector<mc::SynSeg> *segs
     }
     // Dynamic state.
     HIP_TRY(hipMemcpy(nt->u, H.u0.data(), N * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(nt->cur, 0, N * sizeof(float)));
+    HIP_TRY(hipMemcpy(nt->cur, H.i0.data(), N * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(nt->refr, 0, N));
     HIP_TRY(hipMemset(nt->ring, 0, static_cast<size_t>(H.ring) * N * sizeof(int32_t)));
     HIP_TRY(hipMemset(nt->ctl, 0, sizeof(mc::StepCtl)));
@@ -454,14 +470,13 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     if (nt->tile == target && nt->tiled_shape.lds_ring == sh.lds_ring && nt->subrow) return MC_OK;
     HIP_TRY(hipStreamSynchronize(nt->stream));
     for (void *b : {static_cast<void *>(nt->subrow), static_cast<void *>(nt->syn), static_cast<void *>(nt->xchg),
-                    static_cast<void *>(nt->xent), nt->tblk, static_cast<void *>(nt->tiles_dev),
-                    static_cast<void *>(nt->gring)})
+                    static_cast<void *>(nt->xent), static_cast<void *>(nt->dropped), static_cast<void *>(nt->abort_word),
+                    static_cast<void *>(nt->tiles_dev), static_cast<void *>(nt->gring)})
         if (b) hipFree(b);
-    for (void *&b : nt->h_tblk) {
-        if (b) hipHostFree(b);
-        b = nullptr;
-    }
-    nt->tblk = nullptr;
+    if (nt->h_dropped) hipHostFree(nt->h_dropped);
+    nt->h_dropped = nullptr;
+    nt->dropped = nullptr;
+    nt->abort_word = nullptr;
     nt->gring = nullptr;
     nt->gstride = 0;
     nt->subrow = nullptr;
@@ -479,12 +494,9 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
         if ((rc = dalloc(&nt->paths, mc::kPaths))) return rc;
         HIP_TRY(hipMemset(nt->paths, 0, mc::kPaths * sizeof(unsigned long long)));
     }
-    nt->tblk_bytes = sizeof(mc::TiledCtl) + 2 * static_cast<size_t>(T) * sizeof(unsigned long long);
-    {
-        hipError_t e = hipMalloc(&nt->tblk, nt->tblk_bytes);
-        if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    for (void *&b : nt->h_tblk) HIP_TRY(hipHostMalloc(&b, nt->tblk_bytes, hipHostMallocDefault));
+    if ((rc = dalloc(&nt->dropped, 2 * static_cast<size_t>(T))) || (rc = dalloc(&nt->abort_word, 1))) return rc;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_dropped), 2 * static_cast<size_t>(T) * sizeof(unsigned long long),
+                          hipHostMallocDefault));
     if (!sh.lds_ring) {
         nt->gstride = ((tile_max + 31) / 32) * 32;
         if ((rc = dalloc(&nt->gring, static_cast<size_t>(T) * nt->host.ring * nt->gstride))) return rc;
@@ -513,8 +525,13 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     }
     nt->syn_fmt = sf;
     // lanes per spike for cursor delivery: about the mean sub-row length
-    nt->lanes = static_cast<int>(std::min<int64_t>(
-        64, std::max<int64_t>(4, (nt->host.m + std::max<int64_t>(1, sub_total) - 1) / std::max<int64_t>(1, sub_total))));
+    // lanes per spike for cursor delivery: half the mean sub-row length (two or
+    // more records per lane keep more loads in flight; measured at full scale:
+    // 8 lanes deliver 16 % more events per second than 16, 2x more than 32)
+    if (!nt->lanes_set) {
+        const int64_t mean_len = (nt->host.m + std::max<int64_t>(1, sub_total) - 1) / std::max<int64_t>(1, sub_total);
+        nt->lanes = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(4, (mean_len + 1) / 2)));
+    }
     nt->tile = target;
     nt->tiles_host = tiles;
     nt->n_tiles = T;
@@ -743,8 +760,7 @@ int run_tiled(mc_net *nt, int64_t steps)
     tn.poll_delay = nt->poll_delay;
     tn.win = nt->tiled_shape.win;
     tn.xent = nt->xent;
-    tn.tctl = static_cast<mc::TiledCtl *>(nt->tblk);
-    tn.dropped = reinterpret_cast<unsigned long long *>(tn.tctl + 1);
+    tn.abort_word = nt->abort_word;
     tn.spin_limit = nt->spin_limit;
     tn.paths = nt->paths;
     tn.lanes = nt->lanes;
@@ -759,7 +775,10 @@ int run_tiled(mc_net *nt, int64_t steps)
         HIP_TRY(hipMemsetAsync(nt->xent, 0, static_cast<size_t>(2) * T * nt->tile_max * sizeof(uint64_t), nt->stream));
     if (nt->exch_dirty || nt->step < nt->xchg_high || nt->step - nt->xchg_high > kTagSafe)
         HIP_TRY(hipMemsetAsync(nt->xchg, 0, 2 * static_cast<size_t>(T) * sizeof(uint64_t), nt->stream));
-    if (nt->exch_dirty) HIP_TRY(hipMemsetAsync(nt->tblk, 0, nt->tblk_bytes, nt->stream));
+    if (nt->exch_dirty) {
+        for (void *b : nt->rblk) HIP_TRY(hipMemsetAsync(b, 0, sizeof(mc::RecHead), nt->stream));
+        HIP_TRY(hipMemsetAsync(nt->abort_word, 0, sizeof(uint32_t), nt->stream));
+    }
     nt->exch_dirty = false;
     // Segments alternate between the two recorders.  After enqueueing segment k
     // (kernel, then copies of its counters and of the first part of its
@@ -769,30 +788,33 @@ int run_tiled(mc_net *nt, int64_t steps)
     struct Pending {
         int64_t s0, len, copied;
         int buf;
+        bool budget;
     };
-    Pending pend{0, 0, 0, -1};
+    Pending pend{0, 0, 0, -1, false};
     const bool timing = nt->timing;
     auto finish = [nt, timing, T](const Pending &p) -> int {
         HIP_TRY(hipEventSynchronize(nt->snap_ev[p.buf]));
-        const mc::TiledCtl &c = *static_cast<const mc::TiledCtl *>(nt->h_tblk[p.buf]);
-        const unsigned long long *dr = reinterpret_cast<const unsigned long long *>(&c + 1) + static_cast<size_t>(p.buf) * T;
+        const mc::RecHead &c = *static_cast<const mc::RecHead *>(nt->h_rblk[p.buf]);
         if (timing) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, nt->seg_ev0[p.buf], nt->seg_ev1[p.buf]));
             nt->kernel_ms += ms;
             nt->launches += 1;
         }
-        const int64_t total = static_cast<int64_t>(c.rec_total[p.buf]);
+        const int64_t total = static_cast<int64_t>(c.rec_total);
         const int64_t got = std::min(total, nt->rec_cap);
-        if (got > p.copied && !(c.flags[p.buf] & mc::kFlagTimeout)) {
+        if (got > p.copied && !(c.flags & mc::kFlagTimeout)) {
             HIP_TRY(hipMemcpyAsync(nt->h_rec[p.buf] + p.copied, nt->rec[p.buf] + p.copied,
                                    (got - p.copied) * sizeof(uint64_t), hipMemcpyDeviceToHost, nt->copy_stream));
             HIP_TRY(hipStreamSynchronize(nt->copy_stream));
         }
-        for (int k = 0; k < T; ++k)
-            if (dr[k]) nt->inst_dropped[nt->host.meta[nt->tiles_host[k].t0] >> 3] += static_cast<int64_t>(dr[k]);
+        if (p.budget) {
+            const unsigned long long *dr = nt->h_dropped + static_cast<size_t>(p.buf) * T;
+            for (int k = 0; k < T; ++k)
+                if (dr[k]) nt->inst_dropped[nt->host.meta[nt->tiles_host[k].t0] >> 3] += static_cast<int64_t>(dr[k]);
+        }
         const int64_t before = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
-        const int rc = absorb(nt, total, c.flags[p.buf], nt->h_rec[p.buf], p.s0, p.len);
+        const int rc = absorb(nt, total, c.flags, nt->h_rec[p.buf], p.s0, p.len);
         const int64_t after = std::accumulate(nt->inst_spikes.begin(), nt->inst_spikes.end(), int64_t{0});
         if (rc == MC_OK) {
             nt->rec_rate = static_cast<double>(after - before) / std::max<int64_t>(1, p.len);
@@ -810,7 +832,9 @@ int run_tiled(mc_net *nt, int64_t steps)
         const int64_t seg = std::min(steps, nt->seg_steps);
         const int b = nt->next_buf;
         if (++nt->epoch == 0) nt->epoch = 1;
-        tn.buf = b;
+        tn.head = static_cast<mc::RecHead *>(nt->rblk[b]);
+        tn.head_other = static_cast<mc::RecHead *>(nt->rblk[b ^ 1]);
+        tn.dropped = nt->dropped + static_cast<size_t>(b) * T;
         tn.epoch = nt->epoch;
         tn.base.rec = nt->rec[b];
         tn.budget_ticks = nt->budget_ticks;
@@ -819,13 +843,17 @@ int run_tiled(mc_net *nt, int64_t steps)
         if (timing) HIP_TRY(hipEventRecord(nt->seg_ev0[b], nt->stream));
         HIP_TRY(mc::launch_tiled(tn, nt->tiled_shape, seg, nt->coop, nt->stream));
         if (timing) HIP_TRY(hipEventRecord(nt->seg_ev1[b], nt->stream));
-        HIP_TRY(hipMemcpyAsync(nt->h_tblk[b], nt->tblk, nt->tblk_bytes, hipMemcpyDeviceToHost, nt->stream));
-        HIP_TRY(hipMemcpyAsync(nt->h_rec[b], nt->rec[b], guess * sizeof(uint64_t), hipMemcpyDeviceToHost, nt->stream));
+        // one copy: the head and the first `guess` entries
+        HIP_TRY(hipMemcpyAsync(nt->h_rblk[b], nt->rblk[b], sizeof(mc::RecHead) + guess * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, nt->stream));
+        if (tn.budget_ticks)
+            HIP_TRY(hipMemcpyAsync(nt->h_dropped + static_cast<size_t>(b) * T, tn.dropped, T * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, nt->stream));
         HIP_TRY(hipEventRecord(nt->snap_ev[b], nt->stream));
         nt->xent_high = std::max(nt->xent_high, nt->step + seg);
         nt->xchg_high = nt->step + seg;
         if (pend.buf >= 0) rc = finish(pend);
-        pend = {nt->step, seg, guess, b};
+        pend = {nt->step, seg, guess, b, tn.budget_ticks != 0};
         nt->next_buf ^= 1;
         nt->step += seg;
         steps -= seg;
@@ -1161,6 +1189,65 @@ int autotune(mc_net *nt, int64_t trial_steps)
     return restore_snapshot(nt, s);
 }
 
+// Checks shared by the two injection entry points (no allocation): instance,
+// count and ids; *events = the synapses the listed rows hold.
+int inject_check(mc_net *net, int32_t instance, const int32_t *ids, int64_t count, int64_t *events)
+{
+    if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (instance < 0 || instance >= net->host.n_inst) return fail(MC_ERR_ARG, "instance out of range");
+    LIVE_OR_FAIL(net);
+    if (count < 0 || count > (int64_t{1} << 30)) return fail(MC_ERR_ARG, "count out of range");
+    if (count > 0 && !ids) return fail(MC_ERR_ARG, "ids must not be NULL");
+    const int32_t off = net->host.inst_off[instance];
+    const int32_t nn = net->host.inst_off[instance + 1] - off;
+    int64_t ev = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        if (ids[q] < 0 || ids[q] >= nn) return fail(MC_ERR_ARG, "neuron id out of range");
+        ev += static_cast<int64_t>(net->host.row_ptr[off + ids[q] + 1] - net->host.row_ptr[off + ids[q]]);
+    }
+    *events = ev;
+    return MC_OK;
+}
+
+// Copy the instance-local ids into the device array `dev_ids` and deliver the
+// listed rows (checked by inject_check).  Allocates nothing.
+int inject_run(mc_net *net, int32_t instance, const int32_t *ids, int64_t count, int32_t *dev_ids)
+{
+    const int32_t off = net->host.inst_off[instance];
+    HIP_TRY(hipMemcpyAsync(dev_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, net->stream));
+    const mc::DevNet d = dev_view(net);
+    const size_t lds = mc::inject_lds_bytes(net->tile_max, net->host.ring);
+    if (net->timing) HIP_TRY(hipEventRecord(net->ev0, net->stream));
+    if (net->engine == MC_ENGINE_TILED && lds + 256 <= 160 * 1024) {
+        mc::TiledNet tn{};
+        tn.base = d;
+        tn.n_tiles = net->n_tiles;
+        tn.tile_max = net->tile_max;
+        tn.tiles = net->tiles_dev;
+        tn.subrow = net->subrow;
+        tn.syn = net->syn;
+        tn.syn_fmt = net->syn_fmt;
+        tn.lanes = net->lanes;
+        int first = 0;
+        while (net->tiles_host[first].inst_n0 != off) ++first;
+        const int threads = 1024;   // events, not neurons, spread over the threads: more loads in flight
+        HIP_TRY(mc::launch_inject_tiled(tn, first, net->tiles_host[first].intiles, threads, dev_ids,
+                                        static_cast<int32_t>(count), off, net->step, net->stream));
+    } else {
+        HIP_TRY(mc::launch_inject_global(d, dev_ids, static_cast<int32_t>(count), off, net->step, net->stream));
+    }
+    if (net->timing) {
+        HIP_TRY(hipEventRecord(net->ev1, net->stream));
+        HIP_TRY(hipEventSynchronize(net->ev1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, net->ev0, net->ev1));
+        net->kernel_ms += ms;
+        net->launches += 1;
+    }
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    return MC_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1404,7 +1491,12 @@ int mc_set_launch(mc_net *net, const mc_launch *l)
     if (l->deliver_grid < 0) return fail(MC_ERR_ARG, "deliver_grid must be >= 1");
     if (l->poll_delay < -1 || l->poll_delay > 255) return fail(MC_ERR_ARG, "poll_delay must be -1 or in [1, 255]");
     if (l->coop < 0 || l->coop > 2) return fail(MC_ERR_ARG, "coop must be 0 (keep), 1 (cooperative) or 2 (ordinary)");
+    if (l->lanes < 0 || l->lanes > 64) return fail(MC_ERR_ARG, "lanes must be 0 (keep) or in [1, 64]");
     if (l->coop) net->coop = l->coop == 1;
+    if (l->lanes) {
+        net->lanes = l->lanes;
+        net->lanes_set = true;
+    }
     if (l->poll_delay) {
         net->poll_delay = l->poll_delay < 0 ? 0 : l->poll_delay;
         net->poll_delay_set = true;
@@ -1474,7 +1566,8 @@ int mc_set_trace(mc_net *net, int32_t steps)
     net->trace_tiles = 0;
     if (steps == 0) return MC_OK;
     if (net->engine != MC_ENGINE_TILED) return fail(MC_ERR_UNSUPPORTED, "step tracing needs the TILED engine");
-    const size_t count = static_cast<size_t>(steps) * net->n_tiles * mc::kTraceSlots;
+    // the step records plus one row of launch timestamps
+    const size_t count = static_cast<size_t>(steps + 1) * net->n_tiles * mc::kTraceSlots;
     int rc = dalloc(&net->trace, count);
     if (rc) return rc;
     HIP_TRY(hipMemset(net->trace, 0, count * sizeof(uint64_t)));
@@ -1486,7 +1579,7 @@ int mc_set_trace(mc_net *net, int32_t steps)
 int mc_get_trace(mc_net *net, uint64_t *out, int64_t cap, int64_t *count)
 {
     if (!net || !count) return fail(MC_ERR_ARG, "net and count must not be NULL");
-    const int64_t n = static_cast<int64_t>(net->trace_steps) * net->trace_tiles * mc::kTraceSlots;
+    const int64_t n = static_cast<int64_t>(net->trace_steps + (net->trace_steps ? 1 : 0)) * net->trace_tiles * mc::kTraceSlots;
     *count = n;
     if (n == 0) return MC_OK;
     if (!out || cap < n) return fail(MC_ERR_BUFFER_TOO_SMALL, "buffer too small");
@@ -1496,20 +1589,9 @@ int mc_get_trace(mc_net *net, uint64_t *out, int64_t cap, int64_t *count)
 
 int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t count, int64_t *events_out)
 {
-    int64_t nn = 0;
-    int rc = mc_instance_size(net, instance, &nn, nullptr);
-    if (rc) return rc;
-    LIVE_OR_FAIL(net);
-    if (count < 0 || count > (int64_t{1} << 30)) return fail(MC_ERR_ARG, "count out of range");
-    if (count > 0 && !ids) return fail(MC_ERR_ARG, "ids must not be NULL");
-    const int32_t off = net->host.inst_off[instance];
-    std::vector<int32_t> gids(static_cast<size_t>(count));
     int64_t events = 0;
-    for (int64_t q = 0; q < count; ++q) {
-        if (ids[q] < 0 || ids[q] >= nn) return fail(MC_ERR_ARG, "neuron id out of range");
-        gids[q] = ids[q] + off;
-        events += static_cast<int64_t>(net->host.row_ptr[gids[q] + 1] - net->host.row_ptr[gids[q]]);
-    }
+    int rc = inject_check(net, instance, ids, count, &events);
+    if (rc) return rc;
     if (events_out) *events_out = events;
     if (count == 0) return MC_OK;
     if (count > net->inject_cap) {
@@ -1519,38 +1601,7 @@ int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t 
         if ((rc = dalloc(&net->inject_buf, count))) return rc;
         net->inject_cap = count;
     }
-    HIP_TRY(hipMemcpyAsync(net->inject_buf, gids.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, net->stream));
-    const mc::DevNet d = dev_view(net);
-    const size_t lds = mc::inject_lds_bytes(net->tile_max, net->host.ring);
-    if (net->timing) HIP_TRY(hipEventRecord(net->ev0, net->stream));
-    if (net->engine == MC_ENGINE_TILED && lds + 256 <= 160 * 1024) {
-        mc::TiledNet tn{};
-        tn.base = d;
-        tn.n_tiles = net->n_tiles;
-        tn.tile_max = net->tile_max;
-        tn.tiles = net->tiles_dev;
-        tn.subrow = net->subrow;
-        tn.syn = net->syn;
-        tn.syn_fmt = net->syn_fmt;
-        tn.lanes = net->lanes;
-        int first = 0;
-        while (net->tiles_host[first].inst_n0 != off) ++first;
-        const int threads = 1024;   // events, not neurons, spread over the threads: more loads in flight
-        HIP_TRY(mc::launch_inject_tiled(tn, first, net->tiles_host[first].intiles, threads, net->inject_buf,
-                                        static_cast<int32_t>(count), net->step, net->stream));
-    } else {
-        HIP_TRY(mc::launch_inject_global(d, net->inject_buf, static_cast<int32_t>(count), net->step, net->stream));
-    }
-    if (net->timing) {
-        HIP_TRY(hipEventRecord(net->ev1, net->stream));
-        HIP_TRY(hipEventSynchronize(net->ev1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, net->ev0, net->ev1));
-        net->kernel_ms += ms;
-        net->launches += 1;
-    }
-    HIP_TRY(hipStreamSynchronize(net->stream));
-    return MC_OK;
+    return inject_run(net, instance, ids, count, net->inject_buf);
 }
 
 int mc_set_timing(mc_net *net, int32_t on)

@@ -324,6 +324,7 @@ constexpr int kGroupMin = 8;                 // fewest lanes per spike for deliv
 constexpr int kWordIds = 3;                  // spike offsets carried by a tile's word
 constexpr int kDeliverU = 4;                 // records in flight per thread in the step kernel's delivery
 constexpr int kCursorU = 8;                  // and with a cursor over many spikes
+constexpr int kRingBatch = 16;               // ring slots copied per round at launch start and end
 constexpr int kInjectU = 8;                  // and in the injection kernel
 constexpr int kInjBatch = 2048;              // spikes per batch of the injection kernel
 
@@ -423,8 +424,8 @@ __device__ __forceinline__ uint64_t word_make(uint64_t tag, int count) { return 
 // see it and give up too) and flag the time-out for the host.
 __device__ __forceinline__ void give_up(const TiledNet &P)
 {
-    __hip_atomic_store(&P.tctl->abort_epoch, P.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicOr(&P.tctl->flags[P.buf], kFlagTimeout);
+    __hip_atomic_store(P.abort_word, P.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicOr(&P.head->flags, kFlagTimeout);
 }
 
 // Poll *p until `accept(word)`; false if the wait was abandoned: after
@@ -443,7 +444,7 @@ __device__ __forceinline__ bool wait_word(const W *p, const TiledNet &P, Accept 
         w = load_word(p);
         if (accept(w)) return true;
         if ((++spins & 1023u) == 0) {
-            if (__hip_atomic_load(&P.tctl->abort_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == P.epoch)
+            if (__hip_atomic_load(P.abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == P.epoch)
                 return false;
             if (spins > P.spin_limit) {
                 give_up(P);
@@ -660,14 +661,26 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     int *s_src = s_beg;
 
     for (int q = l; q < 8 * kPoisMaxDev; q += nthr) s_thr[q] = B.pois_thr[q];
-    for (int s = 0; s < R; ++s) {
-        if (LRING) {
-            for (int q = l; q < tmax; q += nthr)
-                ring[s * tmax + q] = q < tlen ? B.ring[static_cast<size_t>(s) * B.n + t0 + q] : 0;
-        } else {
-            for (int q = l; q < tlen; q += nthr) gring[s * P.gstride + q] = B.ring[static_cast<size_t>(s) * B.n + t0 + q];
+    // trace form: launch timestamps of this tile (entry, first step, after the
+    // last step, exit) in the row after the step records
+    uint64_t *tr_launch = TRACE && l == 0 && P.trace ? P.trace + (static_cast<size_t>(P.trace_steps) * P.n_tiles + t) * kTraceSlots
+                                                      : nullptr;
+    if (tr_launch) tr_launch[0] = __builtin_amdgcn_s_memrealtime();
+    // The tile's part of the ring, kRingBatch slots' loads in flight at a time
+    // (one dependent round trip per slot would cost the launch tens of us).
+    for (int s0 = 0; s0 < R; s0 += kRingBatch)
+        for (int q = l; q < (LRING ? tmax : tlen); q += nthr) {
+            int v[kRingBatch];
+#pragma unroll
+            for (int k = 0; k < kRingBatch; ++k)
+                v[k] = s0 + k < R && q < tlen ? B.ring[static_cast<size_t>(s0 + k) * B.n + t0 + q] : 0;
+#pragma unroll
+            for (int k = 0; k < kRingBatch; ++k)
+                if (s0 + k < R) {
+                    if (LRING) ring[(s0 + k) * tmax + q] = v[k];
+                    else gring[(s0 + k) * P.gstride + q] = v[k];
+                }
         }
-    }
     for (int q = l; q < W * tmax; q += nthr) ring[q] = 0;
     if (l == 0) {
         s_abort = 0;
@@ -743,6 +756,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     // 4 every tile's word seen, 5 spike ids gathered, 6 delivery done,
     // 7 spike count of the step (this tile's instance).
     uint64_t *tr = nullptr;
+    if (tr_launch) tr_launch[1] = __builtin_amdgcn_s_memrealtime();
     for (int64_t s = 0; s < steps; ++s, ++n) {
         const int par = static_cast<int>(n & 1);
         const uint64_t tag15 = word_tag(n);
@@ -845,7 +859,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         const bool rec_reserve = NPT > 1 && T != P.n_tiles && nspk > 0 && l == nthr - 1;
         unsigned long long rec_reserved = 0;
         if (rec_reserve)
-            rec_reserved = atomicAdd(&P.tctl->rec_total[P.buf], static_cast<unsigned long long>(nspk));
+            rec_reserved = atomicAdd(&P.head->rec_total, static_cast<unsigned long long>(nspk));
         // ---- 3. background input: blocks of step n + 2 into the buffer whose
         // blocks (step n) were all turned into counts before the last barrier;
         // counts of step n + 1 from blocks drawn in the previous step -----------
@@ -862,7 +876,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             for (int q = l; q < nspk; q += nthr) {
                 const int64_t at = s_recbase + q;
                 if (at < B.rec_cap) B.rec[at] = rec_entry(n, s_own[q]);
-                else atomicOr(&P.tctl->flags[P.buf], kFlagRecordOverflow);
+                else atomicOr(&P.head->flags, kFlagRecordOverflow);
             }
         };
         // a range reserved before the wait is filled even when the wait is
@@ -945,13 +959,13 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
             for (int q = l; q < nspk; q += nthr) {
                 const int64_t at = rec_base + s_cnt[tl] + q;
                 if (at < B.rec_cap) B.rec[at] = rec_entry(n, s_own[q]);
-                else atomicOr(&P.tctl->flags[P.buf], kFlagRecordOverflow);
+                else atomicOr(&P.head->flags, kFlagRecordOverflow);
             }
             rec_base += S;
         } else if (nspk) {
             if (NPT == 1) {
                 if (l == 0)
-                    s_recbase = static_cast<long long>(atomicAdd(&P.tctl->rec_total[P.buf],
+                    s_recbase = static_cast<long long>(atomicAdd(&P.head->rec_total,
                                                                  static_cast<unsigned long long>(nspk)));
                 __syncthreads();
             }   // else reserved before the wait (s_recbase written before its barrier)
@@ -1084,6 +1098,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         if (tr) tr[6] = __builtin_amdgcn_s_memrealtime();
     }
 
+    if (tr_launch) tr_launch[2] = __builtin_amdgcn_s_memrealtime();
     // ---- write back state, ring and counters -------------------------------------
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -1098,21 +1113,28 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     __syncthreads();
     // the window rows hold slots n .. n + W - 1 (n: the next step)
     const int n_slot = static_cast<int>(n & mask), n_row = W ? static_cast<int>(n % W) : 0;
-    for (int s2 = 0; s2 < R; ++s2)
+    for (int s0 = 0; s0 < R; s0 += kRingBatch)
         for (int q = l; q < tlen; q += nthr) {
-            int v;
-            if (LRING) {
-                v = ring[s2 * tmax + q];
-            } else {
-                v = gring[s2 * P.gstride + q];
-                const int k = (s2 - n_slot) & mask;
-                if (k < W) {
-                    int row = n_row + k;
-                    if (row >= W) row -= W;
-                    v += ring[row * tmax + q];
-                }
+            int v[kRingBatch];
+#pragma unroll
+            for (int k2 = 0; k2 < kRingBatch; ++k2) {
+                const int s2 = s0 + k2;
+                v[k2] = s2 >= R ? 0 : LRING ? ring[s2 * tmax + q] : gring[s2 * P.gstride + q];
             }
-            B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = v;
+#pragma unroll
+            for (int k2 = 0; k2 < kRingBatch; ++k2) {
+                const int s2 = s0 + k2;
+                if (s2 >= R) continue;
+                if (!LRING) {
+                    const int k = (s2 - n_slot) & mask;
+                    if (k < W) {
+                        int row = n_row + k;
+                        if (row >= W) row -= W;
+                        v[k2] += ring[row * tmax + q];
+                    }
+                }
+                B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = v[k2];
+            }
         }
     unsigned long long ps = pois_sum, dr = drop_acc, ev = ev_acc;
 #pragma unroll
@@ -1133,14 +1155,15 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
     if (l == 0) {
         // this launch's counters: the events this tile dropped (every launch
         // writes its own, so nothing is cleared in between) ...
-        P.dropped[static_cast<size_t>(P.buf) * P.n_tiles + t] = BUDGET ? s_drop : 0ull;
+        P.dropped[t] = BUDGET ? s_drop : 0ull;
         if (t == 0) {
             if (!s_abort) ctl->nbase = n;
-            if (T == P.n_tiles) P.tctl->rec_total[P.buf] = static_cast<unsigned long long>(rec_base);
+            if (T == P.n_tiles) P.head->rec_total = static_cast<unsigned long long>(rec_base);
             // ... and the other buffer's counters, zeroed for the next launch
-            P.tctl->rec_total[P.buf ^ 1] = 0;
-            P.tctl->flags[P.buf ^ 1] = 0;
+            P.head_other->rec_total = 0;
+            P.head_other->flags = 0;
         }
+        if (tr_launch) tr_launch[3] = __builtin_amdgcn_s_memrealtime();
     }
 }
 
@@ -1308,7 +1331,8 @@ namespace {
 // One workgroup per tile: gather the tile's sub-rows of all listed neurons,
 // accumulate into an LDS copy of the tile's ring, then add it into the ring.
 template <int SF>
-__global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t *ids, int32_t count, int64_t n)
+__global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t *ids, int32_t count, int32_t id_offset,
+                                                       int64_t n)
 {
     extern __shared__ int lds[];
     const DevNet &B = P.base;
@@ -1325,7 +1349,7 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     for (int b0 = 0; b0 < count; b0 += kInjBatch) {
         const int nb = min(kInjBatch, count - b0);
         for (int q = l; q < nb; q += nthr) {
-            const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(ids[b0 + q] - td.inst_n0) * td.intiles];
+            const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(ids[b0 + q] + id_offset - td.inst_n0) * td.intiles];
             s_beg[q] = static_cast<int>(sr.x);
             s_len[q] = static_cast<int>(sr.y);
         }
@@ -1335,22 +1359,31 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
         });
         __syncthreads();
     }
-    for (int s = 0; s < R; ++s)
+    // add the staged ring into the global one, kRingBatch slots in flight
+    for (int s0 = 0; s0 < R; s0 += kRingBatch)
         for (int q = l; q < tlen; q += nthr) {
-            const int v = ring[s * tmax + q];
-            if (v) B.ring[static_cast<size_t>(s) * B.n + td.t0 + q] += v;
+            int v[kRingBatch], g[kRingBatch];
+#pragma unroll
+            for (int k = 0; k < kRingBatch; ++k) {
+                v[k] = s0 + k < R ? ring[(s0 + k) * tmax + q] : 0;
+                g[k] = v[k] ? B.ring[static_cast<size_t>(s0 + k) * B.n + td.t0 + q] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kRingBatch; ++k)
+                if (v[k]) B.ring[static_cast<size_t>(s0 + k) * B.n + td.t0 + q] = g[k] + v[k];
         }
 }
 
 // Fallback: one wavefront per listed neuron's row chunk of `seg` synapses,
 // device-scope int32 atomics into the global ring.
 template <int WF>
-__global__ __launch_bounds__(256) void k_inject_global(DevNet P, const int32_t *ids, int32_t count, int64_t n)
+__global__ __launch_bounds__(256) void k_inject_global(DevNet P, const int32_t *ids, int32_t count, int32_t id_offset,
+                                                      int64_t n)
 {
     const int lane = threadIdx.x & 63;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * 4;
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); w < count; w += waves) {
-        const int32_t pre = ids[w];
+        const int32_t pre = ids[w] + id_offset;
         const uint64_t j0 = P.row_ptr[pre], j1 = P.row_ptr[pre + 1];
         for (uint64_t j = j0 + lane; j < j1; j += 64) {
             const int d = P.dly[j];
@@ -1370,7 +1403,7 @@ size_t inject_lds_bytes(int tile_max, int ring)
 }
 
 hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
-                               int32_t count, int64_t n, hipStream_t st)
+                               int32_t count, int32_t id_offset, int64_t n, hipStream_t st)
 {
     TiledNet arg = tn;
     arg.tile_offset = first_tile;
@@ -1381,18 +1414,19 @@ hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, i
                   : tn.syn_fmt == kSyn4F16 ? inject_tiled_fn<kSyn4F16>() : inject_tiled_fn<kSyn4BF16>();
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    void *args[] = {&arg, const_cast<int32_t **>(&ids), &count, &n};
+    void *args[] = {&arg, const_cast<int32_t **>(&ids), &count, &id_offset, &n};
     return hipLaunchKernel(f, dim3(ntiles), dim3(threads), args, lds, st);
 }
 
-hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int64_t n, hipStream_t st)
+hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int32_t id_offset, int64_t n,
+                                hipStream_t st)
 {
     const int blocks = static_cast<int>(std::min<int64_t>(4096, (static_cast<int64_t>(count) + 3) / 4));
     if (blocks < 1) return hipSuccess;
     switch (d.wfmt) {
-    case 0: hipLaunchKernelGGL(k_inject_global<0>, dim3(blocks), dim3(256), 0, st, d, ids, count, n); break;
-    case 1: hipLaunchKernelGGL(k_inject_global<1>, dim3(blocks), dim3(256), 0, st, d, ids, count, n); break;
-    default: hipLaunchKernelGGL(k_inject_global<2>, dim3(blocks), dim3(256), 0, st, d, ids, count, n); break;
+    case 0: hipLaunchKernelGGL(k_inject_global<0>, dim3(blocks), dim3(256), 0, st, d, ids, count, id_offset, n); break;
+    case 1: hipLaunchKernelGGL(k_inject_global<1>, dim3(blocks), dim3(256), 0, st, d, ids, count, id_offset, n); break;
+    default: hipLaunchKernelGGL(k_inject_global<2>, dim3(blocks), dim3(256), 0, st, d, ids, count, id_offset, n); break;
     }
     return hipGetLastError();
 }

@@ -60,14 +60,14 @@ __host__ __device__ inline uint64_t rec_entry(int64_t step, int32_t id)
     return (static_cast<uint64_t>(static_cast<uint32_t>(step)) << 32) | static_cast<uint32_t>(id);
 }
 
-// Per-launch counters of the tiled engine.  Launches alternate between two
-// recorder buffers; each set is zeroed by the launch that uses the other buffer,
-// so the host never clears them between launches.
-struct TiledCtl {
-    unsigned long long rec_total[2];  // spikes recorded into buffer b by the launch using it
-    uint32_t flags[2];                // kFlag* of the launch using buffer b
-    uint32_t abort_epoch;             // epoch of a launch in which a wait gave up
-    uint32_t pad;
+// Head of a spike-recorder buffer (the entries follow it): the counters of the
+// tiled launch that records into it.  Launches alternate between two buffers
+// and each launch zeroes the other buffer's head, so the host clears nothing
+// between launches and copies one head plus entries per launch.
+struct RecHead {
+    unsigned long long rec_total;     // spikes recorded by the launch
+    uint32_t flags;                   // kFlag* of the launch
+    uint32_t pad[13];                 // 64 bytes
 };
 
 // Tiled persistent engine.  Tiles are ranges of consecutive neurons that never
@@ -105,14 +105,15 @@ struct TiledNet {
     int32_t poll_delay;               // sleep before the first poll of a step, in units of 64 clocks
     uint64_t *xchg;                   // [2][n_tiles] per-step tile words (tag | count | first three offsets)
     uint64_t *xent;                   // [2][n_tiles][tile_max] further spike ids (tag32 | id)
-    TiledCtl *tctl;                   // per-launch counters, abort word
-    int32_t buf;                      // recorder buffer of this launch (0 or 1)
+    RecHead *head;                    // this launch's recorder head (entries: base.rec)
+    RecHead *head_other;              // the other buffer's head, zeroed for the next launch
+    uint32_t *abort_word;             // epoch of a launch in which a wait gave up
     uint32_t epoch;                   // launch number (never 0): the abort word names the launch
     uint32_t spin_limit;              // polls before a wait gives up (0: at once)
     uint64_t *trace;                  // optional [trace_steps][n_tiles][8] phase timestamps
     int32_t trace_steps;
     int32_t gstride;                  // global-ring variant: ints per slot row (multiple of 32)
-    unsigned long long *dropped;      // [2][n_tiles] events dropped by the step budget, per buffer
+    unsigned long long *dropped;      // [n_tiles] events dropped by the step budget in this launch
     unsigned long long *paths;        // [kPaths] tile-steps per delivery path, summed over launches
     uint32_t budget_ticks;            // step budget in 100 MHz clock ticks; 0: none
     int32_t win;                      // global-ring variant: LDS window of the nearest `win` slots (< R)
@@ -166,9 +167,11 @@ hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_
 // Spike injection (external stimulation): deliver the rows of `ids` as if they
 // spiked in step n-1.  Tiled form needs the tile ring to fit in LDS.
 size_t inject_lds_bytes(int tile_max, int ring);
+// ids: device array of instance-local ids; id_offset: the instance's first global id.
 hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
-                               int32_t count, int64_t n, hipStream_t st);
-hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int64_t n, hipStream_t st);
+                               int32_t count, int32_t id_offset, int64_t n, hipStream_t st);
+hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t count, int32_t id_offset, int64_t n,
+                                hipStream_t st);
 // Device-side construction of the tiled engine's sub-row table and packed
 // synapse store (rows sorted by target; tile_of: tile index of every neuron).
 hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t n_neurons, uint2 *subrow,

@@ -24,6 +24,7 @@ struct ModelParams {
     double nu_bg_hz, dt_ms, tau_m_ms, c_m_pf, tau_syn_ms, t_ref_ms, theta_mv;
     double w_mean_pa, w_sd_pa, g, l4e_l23e_factor, w_ext_pa;
     double d_mean_exc_ms, d_sd_exc_ms, d_mean_inh_ms, d_sd_inh_ms;
+    double init_u_mean[kPops], init_u_sd[kPops], init_i_mean[kPops], init_i_sd[kPops];   // relaxed start
     int32_t wfmt, poisson_on, init_mode;
 };
 
@@ -54,6 +55,7 @@ struct HostNet {
     std::vector<uint16_t> w16;        // [M] FP16/BF16 bits (reduced-precision stores)
     std::vector<uint8_t> d;           // [M] delay in steps
     std::vector<float> u0;            // [N] initial u
+    std::vector<float> i0;            // [N] initial synaptic current
     int32_t ring = 2;                 // power of two > max delay
 };
 
@@ -75,6 +77,9 @@ int build_host_network(const ModelParams &p, const uint64_t *seeds, const double
 // metadata and initial state.  H.row_ptr, tgt, wq, w16, d and ring stay empty.
 int plan_network(const ModelParams &p, const uint64_t *seeds, const double *scales, int32_t n_inst, HostNet &H,
                  std::vector<SynSeg> &segs, std::string &msg);
+
+// Relaxed initial state (init_mode 2) of instance-local neuron `local` of population a.
+void relaxed_start(const ModelParams &p, uint64_t local, int a, uint64_t seed, double &u, double &cur);
 
 // Reduced-precision rounding (round-to-nearest-even from double), as bit patterns.
 uint16_t half_bits_rne(double x);

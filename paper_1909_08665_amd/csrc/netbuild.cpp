@@ -179,6 +179,36 @@ void derive_constants(const ModelParams &p, StepConstants &c)
     }
 }
 
+// Relaxed initial state of neuron `local` of population a (init_mode 2; the
+// paper starts from potentials that make the first steps look like the steady
+// state, Sec. 4a).  Block (local, 1 + r, 0, kTagInit) gives a normal pair by
+// Box-Muller on words 0 and 1 and a uniform in word 2.  The synaptic current
+// is i_mean + i_sd * (second normal of the first block).  The potential is
+// u_mean + u_sd * (first normal) of the first block r whose value lies below
+// theta and whose uniform passes 1 - exp(-2 (theta - u)(theta - u_mean) / u_sd^2):
+// the normal density minus its mirror image in the threshold, which vanishes
+// at theta as the steady state's does.
+void relaxed_start(const ModelParams &p, uint64_t local, int a, uint64_t seed, double &u, double &cur)
+{
+    const double mu = p.init_u_mean[a], sd = p.init_u_sd[a], th = p.theta_mv;
+    const double two_pi = 6.283185307179586;
+    u = 0.0;
+    cur = 0.0;
+    for (uint64_t r = 0; r < 64; ++r) {
+        const Block4 x = philox_host(local, 1 + r, 0, kTagInit, seed);
+        const double radius = std::sqrt(-2.0 * std::log(unit_open_low(x.v[0])));
+        const double angle = two_pi * unit_open_high(x.v[1]);
+        const double z1 = radius * std::cos(angle);
+        if (r == 0) cur = p.init_i_mean[a] + p.init_i_sd[a] * (radius * std::sin(angle));
+        const double v = mu + sd * z1;
+        const double accept = 1.0 - std::exp(-2.0 * (th - v) * (th - mu) / (sd * sd));
+        if (v < th && unit_open_high(x.v[2]) < accept) {
+            u = v;
+            return;
+        }
+    }
+}
+
 // ---- network ------------------------------------------------------------------
 int plan_network(const ModelParams &p, const uint64_t *seeds, const double *scales, int32_t n_inst, HostNet &out,
                  std::vector<SynSeg> &segs, std::string &msg)
@@ -248,13 +278,23 @@ int plan_network(const ModelParams &p, const uint64_t *seeds, const double *scal
             }
     }
 
-    // Initial membrane potentials u ~ U[0, theta) (or zero).
+    // Initial state: u ~ U[0, theta) (init_mode 0), all zero (1), or the relaxed
+    // start (2).
     H.u0.assign(n_total, 0.0f);
+    H.i0.assign(n_total, 0.0f);
     if (p.init_mode == 0) {
         for (int j = 0; j < n_inst; ++j)
             for (int32_t i = H.inst_off[j]; i < H.inst_off[j + 1]; ++i) {
                 const Block4 x = philox_host(static_cast<uint64_t>(i - H.inst_off[j]), 0, 0, kTagInit, H.seeds[j]);
                 H.u0[i] = static_cast<float>(p.theta_mv * unit_open_high(x.v[0]));
+            }
+    } else if (p.init_mode == 2) {
+        for (int j = 0; j < n_inst; ++j)
+            for (int32_t i = H.inst_off[j]; i < H.inst_off[j + 1]; ++i) {
+                double u = 0.0, cur = 0.0;
+                relaxed_start(p, static_cast<uint64_t>(i - H.inst_off[j]), static_cast<int>(H.meta[i] & 7u), H.seeds[j], u, cur);
+                H.u0[i] = static_cast<float>(u);
+                H.i0[i] = static_cast<float>(cur);
             }
     }
     return MC_OK;

@@ -9,7 +9,7 @@ microbenchmark, and stand-in amplitudes for the DC-input workload.
 """
 from .conn_table import (FULL_SIZE, K_EXT, POP_NAMES, STANDIN_SEED, standin_conn_table,
                          standin_description)
-from .workloads import batch_scales, dc_standin_amplitudes, forced_spike_list
+from .workloads import batch_scales, dc_standin_amplitudes, forced_spike_list, relaxed_start
 
 __all__ = ["FULL_SIZE", "K_EXT", "POP_NAMES", "STANDIN_SEED", "standin_conn_table",
-           "standin_description", "batch_scales", "dc_standin_amplitudes", "forced_spike_list"]
+           "standin_description", "batch_scales", "dc_standin_amplitudes", "forced_spike_list", "relaxed_start"]

@@ -4,7 +4,24 @@ from __future__ import annotations
 
 import numpy as np
 
+import json
+import os
+
 from .conn_table import FULL_SIZE, K_EXT
+
+_RELAXED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "relaxed_start.json")
+
+
+def relaxed_start():
+    """Inputs of the relaxed initial state (init_mode 2) for the stand-in
+    network: per-population mean and standard deviation of the membrane
+    potential and of the synaptic current in its steady state, as keyword
+    arguments of the library's and the oracle's configurations.  The values
+    (relaxed_start.json) were measured on the oracle's run of the full-scale
+    network; the file names how."""
+    r = json.load(open(_RELAXED))
+    return dict(init_mode=2, init_u_mean_mv=r["u_mean"], init_u_sd_mv=r["u_sd"],
+                init_i_mean_pa=r["i_mean"], init_i_sd_pa=r["i_sd"])
 
 
 def batch_scales(n: int, lo: float, hi: float, seed: int):

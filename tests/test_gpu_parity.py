@@ -412,6 +412,25 @@ def test_ordinary_launch_parity(conn):
         assert _same_run(net, orc) > 0
 
 
+@pytest.mark.parametrize("scale,steps", [(0.02, 2000), (1.0, 500)])
+def test_relaxed_start_parity(conn, scale, steps):
+    """The relaxed initial state (init_mode 2: per-population moments of u and
+    I from the stand-in's steady state) drawn by the library equals the
+    oracle's, and the run from it too."""
+    from synth_inputs import relaxed_start
+    _say("relaxed start", scale)
+    kw = relaxed_start()
+    net = mc.Network.build(5, scale, conn, **kw)
+    orc = _oracle(5, scale, conn, **kw)
+    u, I, r = net.state()
+    ru, rI, rr = orc.state()
+    assert np.array_equal(u.astype(np.float64), ru) and np.array_equal(I.astype(np.float64), rI)
+    assert u.max() < 15.0 and I.std() > 0
+    net.run(steps)
+    orc.run(steps)
+    assert _same_run(net, orc) > 0
+
+
 def test_checkpoint_resume_is_bit_exact(conn, tmp_path):
     _say("checkpoint")
     path = str(tmp_path / "net.ckpt")

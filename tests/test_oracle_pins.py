@@ -488,3 +488,56 @@ def test_overflow_bound_microcircuit(conn_table):
         O.OracleNet.build(1, 0.1, conn_table.reshape(64), p)
     # a tenth of that weight fits
     assert O.OracleNet.build(1, 0.1, conn_table.reshape(64), O.default_params(w_mean_pa=1.5e3)).M > 0
+
+
+RELAXED = dict(u_mean=[5.0, 5.7, 5.1, 5.9, 5.5, 6.1, 3.4, 5.0], u_sd=[3.9, 3.8, 3.9, 3.7, 3.8, 3.6, 4.4, 3.9],
+               i_mean=[355.0, 368.0, 354.0, 371.0, 367.0, 371.0, 344.0, 364.0],
+               i_sd=[455.0, 450.0, 457.0, 446.0, 449.0, 457.0, 511.0, 451.0])
+
+
+def _relaxed_params(mode=O.MIRROR, r=RELAXED):
+    return O.default_params(mode=mode, init_mode=2, init_u_mean_mv=r["u_mean"], init_u_sd_mv=r["u_sd"],
+                            init_i_mean_pa=r["i_mean"], init_i_sd_pa=r["i_sd"])
+
+
+@pytest.mark.parametrize("mode", [O.MIRROR, O.FP64])
+def test_relaxed_start_brute_force_equals_oracle(mode):
+    """The relaxed initial state (init_mode 2) drawn by the oracle equals the
+    brute-force draw, and the run from it too."""
+    sizes, pre, post, w, d = _tiny_net(51)
+    orc = O.OracleNet.build_explicit(sizes, pre, post, w, d, params=_relaxed_params(mode), seed=77)
+    bf = brute.BruteNet(sizes, pre, post, w, d, seed=77, fp64=(mode == O.FP64), relaxed=RELAXED)
+    u, I, r = orc.state()
+    assert np.array_equal(u, np.array(bf.u, dtype=np.float64))
+    assert np.array_equal(I, np.array(bf.I, dtype=np.float64))
+    orc.run(200)
+    bf.run(200)
+    st, ids = orc.spikes()
+    assert list(zip(st.tolist(), ids.tolist())) == bf.spikes
+
+
+def test_relaxed_start_distribution():
+    """u follows the normal density minus its image in the threshold (zero at
+    theta, below it everywhere), I the normal: checked on 200,000 draws against
+    the closed-form density and moments."""
+    r = dict(u_mean=[5.0] * 8, u_sd=[4.0] * 8, i_mean=[350.0] * 8, i_sd=[450.0] * 8)
+    net = O.OracleNet.build_explicit([25000] * 8, [], [], [], [], params=_relaxed_params(O.FP64, r), seed=3)
+    u, I, _ = net.state()
+    th, mu, sd = 15.0, 5.0, 4.0
+    assert u.max() < th
+    # I: normal moments
+    assert abs(I.mean() - 350.0) < 5 * 450 / math.sqrt(len(I))
+    assert abs(I.std() / 450.0 - 1) < 5 / math.sqrt(2 * len(I))
+    # u: histogram against the image density phi(u; mu) - phi(u; 2 th - mu), normalised below th
+    edges = np.linspace(-15.0, 15.0, 31)
+    cdf = lambda x: stats.norm.cdf(x, mu, sd) - stats.norm.cdf(x, 2 * th - mu, sd)
+    mass = np.diff(cdf(edges))
+    mass[0] += cdf(edges[0])                                  # everything below the first edge
+    mass /= cdf(th)
+    obs = np.histogram(np.clip(u, edges[0], edges[-1]), bins=edges)[0]
+    exp = mass * len(u)
+    keep = exp > 20
+    chi2 = ((obs[keep] - exp[keep]) ** 2 / exp[keep]).sum()
+    assert stats.chi2.sf(chi2, keep.sum() - 1) > 1e-4
+    # near the threshold the density vanishes: the top 0.5 mV holds far fewer than a plain normal would
+    assert (u > th - 0.5).mean() < 0.25 * (stats.norm.cdf(th, mu, sd) - stats.norm.cdf(th - 0.5, mu, sd))
