@@ -71,6 +71,47 @@ def cpu_baseline(seed, scale, conn, warm, steps, i_dc=None, single_steps=0, init
     return out
 
 
+def cpu_survey(conn, init_kw):
+    """The oracle (FP32 mirror) on the 2 % network (10^4 steps), one 10 %
+    instance of the batch workload and the full network (bounded samples after a
+    warm-up), each on every core and on one thread: real-time factor and
+    recurrent events/s.  Host model and core count are reported."""
+    import platform
+
+    from oracle import oracle as O
+    cores = O.max_threads()
+    model = ""
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        model = platform.processor()
+    rows = []
+    for name, seed, scale, warm, steps, steps1 in (("2 % (1,544 neurons)", 1, 0.02, 1000, 10000, 10000),
+                                                   ("10 % instance of the batch (7,718 neurons)", 1000, 0.1, 1000, 5000, 2000),
+                                                   ("full scale (77,169 neurons)", 1, 1.0, 1000, 3000, 200)):
+        t = time.time()
+        net = O.OracleNet.build(seed, scale, conn.reshape(64), O.default_params(**init_kw))
+        build_s = time.time() - t
+        net.run(warm)
+        net.spikes(clear=True)
+        row = {"workload": name, "scale": scale, "seed": seed, "build_s": round(build_s, 2)}
+        for threads, n in ((cores, steps), (1, steps1)):
+            O.set_threads(threads)
+            c0 = net.counters()
+            t0 = time.perf_counter()
+            net.run(n)
+            wall = time.perf_counter() - t0
+            net.spikes(clear=True)
+            ev = net.counters()["events"] - c0["events"]
+            row[f"threads_{threads}"] = {"steps": n, "rtf": round(n * DT_S / wall, 5), "events_per_s": round(ev / wall, 1)}
+            log(f"oracle {name}: {threads} threads, {n} steps in {wall:.2f}s -> RTF {n * DT_S / wall:.4f}")
+        O.set_threads(cores)
+        rows.append(row)
+        del net
+    return {"metric": "oracle (FP32 mirror) real-time factor on the host", "cores": cores, "cpu": model,
+            "kind": "oracle", "rows": rows}
+
+
 PHASES = (("update+publish", 0, 1), ("wait for all tiles", 3, 4),
           ("spike ids + sub-row entries", 4, 5), ("delivery", 5, 6))
 
@@ -88,6 +129,11 @@ def step_latency(net):
     skew = (launch[:, 0].max() - launch[:, 0].min()) * 0.01
     log(f"  launch: prologue max {prologue.max():.2f} us, epilogue max {epilogue.max():.2f} us, "
         f"start skew over tiles {skew:.2f} us")
+    if launch.shape[1] >= 7:
+        for name, a, b in (("state stores + barrier", 2, 4), ("ring stores", 4, 5), ("counter atomics", 5, 6),
+                           ("path counters, heads", 6, 3)):
+            d = (launch[:, b] - launch[:, a]) * 0.01
+            log(f"    epilogue {name:24s} mean {d.mean():7.3f} us  max {d.max():7.3f} us")
     tr[:, :, 5] = np.where(tr[:, :, 5] == 0, tr[:, :, 4], tr[:, :, 5])   # steps without spikes
     per = np.diff(tr[:, :, 0], axis=0).max(axis=1) * 0.01                # us, slowest tile
     phases = {}
@@ -276,6 +322,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-warm", type=int, default=1000)
     ap.add_argument("--cpu-steps", type=int, default=5000)
+    ap.add_argument("--cpu-survey", action="store_true",
+                    help="only time the oracle on the host: 2 %%, one 10 %% instance, full scale; all cores and one")
     ap.add_argument("--cpu-single-steps", type=int, default=300,
                     help="oracle steps timed on one thread after the multi-thread sample (0: none)")
     ap.add_argument("--d1", action="store_true",
@@ -290,6 +338,11 @@ def main():
     if args.wfmt is None:
         args.wfmt = "fp16" if args.config == "uneven32" else "fp32"
 
+    if args.cpu_survey:
+        from synth_inputs import relaxed_start, standin_conn_table
+        kw = relaxed_start() if args.init == "relaxed" else {"init_mode": INIT_MODES[args.init]}
+        print(json.dumps(cpu_survey(standin_conn_table(), kw)), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(independent instances would shard across GPUs with no exchange)", file=sys.stderr)

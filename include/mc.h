@@ -324,7 +324,8 @@ int mc_get_timing(struct mc_net *net, double *kernel_ms, int64_t *launches);
  * spike counts gathered, delivery done, and the step's spike count; then one
  * more row per tile with the launch's own timestamps: kernel entry, start of
  * the first step (after the ring and state are loaded), end of the last step,
- * and the end of the write-back.  k = 0 disables it.  mc_get_trace copies
+ * end of the write-back, then within the write-back: state stored, ring
+ * stored, counters added.  k = 0 disables it.  mc_get_trace copies
  * [k + 1][n_tiles][8] words into `out` (cap entries) and sets *count;
  * MC_ERR_BUFFER_TOO_SMALL if cap is too small.
  */

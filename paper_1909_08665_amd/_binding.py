@@ -278,7 +278,7 @@ class Network:
         info = self.info()
         rows = out.reshape(-1, max(1, info["n_tiles"]), 8)
         steps = rows[:-1] if len(rows) else rows
-        return (steps, rows[-1, :, :4] if len(rows) else None) if launch else steps
+        return (steps, rows[-1, :, :7] if len(rows) else None) if launch else steps
 
     def save(self, path):
         _check(lib().mc_save_state(self._h, os.fsencode(path)))

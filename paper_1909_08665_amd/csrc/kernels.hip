@@ -1111,6 +1111,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         }
     }
     __syncthreads();
+    if (tr_launch) tr_launch[4] = __builtin_amdgcn_s_memrealtime();
     // the window rows hold slots n .. n + W - 1 (n: the next step)
     const int n_slot = static_cast<int>(n & mask), n_row = W ? static_cast<int>(n % W) : 0;
     for (int s0 = 0; s0 < R; s0 += kRingBatch)
@@ -1136,6 +1137,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
                 B.ring[static_cast<size_t>(s2) * B.n + t0 + q] = v[k2];
             }
         }
+    if (tr_launch) tr_launch[5] = __builtin_amdgcn_s_memrealtime();
     unsigned long long ps = pois_sum, dr = drop_acc, ev = ev_acc;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1149,6 +1151,7 @@ __global__ __launch_bounds__(1024) void k_tiled(TiledNet P, int64_t steps)
         if ((l & 63) == 0 && dr) atomicAdd(&s_drop, dr);
         __syncthreads();
     }
+    if (tr_launch) tr_launch[6] = __builtin_amdgcn_s_memrealtime();
     if (l == 0)
         for (int k = 0; k < kPaths; ++k)
             if (s_paths[k]) atomicAdd(&P.paths[k], static_cast<unsigned long long>(s_paths[k]));

@@ -7,8 +7,9 @@ steps already look like the steady state, instead of the transient a uniform
 start gives (Sec. 4a); its values are not given.  Here they are measured: the
 oracle (FP32 mirror) runs the network of seed 1 from the uniform start for
 2 s, then the mean and standard deviation of u (neurons not refractory) and of
-the synaptic current I of every population are averaged over ten snapshots
-taken 10 ms apart.
+the synaptic current I of every population are averaged over forty snapshots
+taken 3.7 ms apart (not a multiple of the network's oscillation period, so the
+snapshots sample its phases).
 
 Calls only oracle/ (and the seeded input generator):
     python tests/golden/make_relaxed_start.py
@@ -26,7 +27,7 @@ from oracle import oracle as O                      # noqa: E402
 from synth_inputs import standin_conn_table, standin_description   # noqa: E402
 
 OUT = os.path.join(ROOT, "synth_inputs", "relaxed_start.json")
-SETTLE, SNAPS, GAP = 20000, 10, 100
+SETTLE, SNAPS, GAP = 20000, 40, 37
 
 
 def main():
