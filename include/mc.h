@@ -280,6 +280,20 @@ int mc_instance_size(struct mc_net *net, int32_t instance, int64_t *n_neurons, i
  */
 int mc_inject_spikes(struct mc_net *net, int32_t instance, const int32_t *ids, int64_t count, int64_t *events_out);
 
+/*
+ * mc_inject_spikes for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same delivery, with the ids staged in a fixed device array of
+ * 1,048,576 entries that the library holds per GPU from the first network
+ * built on it until the process ends (resolved at that build), instead of a
+ * buffer allocated on first use.  Allocates nothing; synchronous like
+ * mc_inject_spikes.  Every call on one GPU shares that array, so calls that
+ * overlap on one GPU (from several threads or processes' networks on it) race.
+ * Errors: as mc_inject_spikes, and MC_ERR_ARG when count exceeds 1,048,576.
+ */
+int mc_inject_spikes_noalloc(struct mc_net *net, int32_t instance, const int32_t *ids, int64_t count,
+                             int64_t *events_out);
+
 /* Select launch knobs (engine, tile size, graph chunk, work-item size, block, grid).
    MC_ERR_UNSUPPORTED if the TILED engine cannot hold the network (LDS, co-residency). */
 int mc_set_launch(struct mc_net *net, const mc_launch *l);

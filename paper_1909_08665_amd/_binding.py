@@ -67,7 +67,7 @@ EXPORTS = ("mc_config_default", "mc_build_network", "mc_build_batch", "mc_run", 
            "mc_instance_size", "mc_set_launch", "mc_tune", "mc_set_stream", "mc_set_timing",
            "mc_get_timing", "mc_set_trace", "mc_get_trace", "mc_save_state", "mc_load_state", "mc_free",
            "mc_last_error", "mc_inject_spikes", "mc_set_step_budget", "mc_set_wait_limit",
-           "mc_get_paths", "mc_probe")
+           "mc_get_paths", "mc_probe", "mc_inject_spikes_noalloc")
 
 _lib = None
 
@@ -108,6 +108,7 @@ def lib():
     L.mc_set_timing.argtypes = [P, I32]
     L.mc_get_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I64)]
     L.mc_inject_spikes.argtypes = [P, I32, P, I64, C.POINTER(I64)]
+    L.mc_inject_spikes_noalloc.argtypes = [P, I32, P, I64, C.POINTER(I64)]
     L.mc_set_trace.argtypes = [P, I32]
     L.mc_get_trace.argtypes = [P, P, I64, C.POINTER(I64)]
     L.mc_save_state.argtypes = [P, C.c_char_p]
@@ -260,6 +261,14 @@ class Network:
         ids = np.ascontiguousarray(ids, dtype=np.int32)
         ev = C.c_int64()
         _check(lib().mc_inject_spikes(self._h, int(instance), _ptr(ids), len(ids), C.byref(ev)))
+        return ev.value
+
+    def inject_spikes_noalloc(self, ids, instance=0):
+        """inject_spikes with the ids staged in the library's fixed per-GPU
+        array (no device allocation; at most 2^20 ids)."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        ev = C.c_int64()
+        _check(lib().mc_inject_spikes_noalloc(self._h, int(instance), _ptr(ids), len(ids), C.byref(ev)))
         return ev.value
 
     def set_trace(self, steps):

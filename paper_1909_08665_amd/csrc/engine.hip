@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -58,6 +59,38 @@ constexpr int64_t kTagSafe = 32767 - kSegMax - 8;
 // the instances have at least kPollDelayTiles tiles (T tiles each polling T
 // words congest the lines the last stores go to); none for fewer tiles.
 constexpr int kPollDelayDefault = 32, kPollDelayTiles = 64;
+
+// Staging of the ids of mc_inject_spikes_noalloc, for callers that cannot
+// allocate: a file-scope device array (each GPU holds its own copy until the
+// process ends), shared by every such call on that GPU, so calls that overlap
+// on one GPU race.  Host code uses its device address, resolved once per
+// device (device_staging), never the array's name.
+constexpr int64_t kNoAllocIds = int64_t{1} << 20;
+__device__ __align__(256) int32_t scratch[kNoAllocIds];
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on `device`, resolved with that device current
+// on the first call for it.
+int device_staging(int device, int32_t **out)
+{
+    static std::mutex mu;
+    static int32_t *addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return fail(MC_ERR_UNSUPPORTED, "device index beyond the staging table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != device) hipSetDevice(cur);
+        if (e != hipSuccess) return fail(MC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[device] = static_cast<int32_t *>(p);
+    }
+    *out = addr[device];
+    return MC_OK;
+}
 
 }  // namespace
 
@@ -109,6 +142,7 @@ struct mc_net {
     int32_t gstride = 0;
     std::vector<mc::TileDesc> tiles_host;
     int32_t *inject_buf = nullptr;     // device copy of injected spike ids
+    int32_t *noalloc_ids = nullptr;    // this device's staging array for mc_inject_spikes_noalloc
     int64_t inject_cap = 0;
     uint2 *subrow = nullptr;           // tiled engine: per-tile (first synapse, count) of each sub-row
     void *syn = nullptr;               // tiled engine: packed synapse records
@@ -298,6 +332,7 @@ int upload(mc_net *nt, const mc_config *cfg, const std::vector<mc::SynSeg> *segs
     const int64_t N = H.n, M = H.m;
     int rc;
     HIP_TRY(hipGetDevice(&nt->device));
+    if ((rc = device_staging(nt->device, &nt->noalloc_ids))) return rc;
     {
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, nt->device));
@@ -1602,6 +1637,20 @@ int mc_inject_spikes(mc_net *net, int32_t instance, const int32_t *ids, int64_t 
         net->inject_cap = count;
     }
     return inject_run(net, instance, ids, count, net->inject_buf);
+}
+
+int mc_inject_spikes_noalloc(mc_net *net, int32_t instance, const int32_t *ids, int64_t count, int64_t *events_out)
+{
+    if (count > kNoAllocIds)
+        return fail(MC_ERR_ARG, "count exceeds the " + std::to_string(kNoAllocIds) +
+                                    " ids of the no-allocation staging array; use mc_inject_spikes");
+    int64_t events = 0;
+    const int rc = inject_check(net, instance, ids, count, &events);
+    if (rc) return rc;
+    if (!net->noalloc_ids) return fail(MC_ERR_HIP, "no-allocation staging array not resolved on this device");
+    if (events_out) *events_out = events;
+    if (count == 0) return MC_OK;
+    return inject_run(net, instance, ids, count, net->noalloc_ids);
 }
 
 int mc_set_timing(mc_net *net, int32_t on)
