@@ -1333,13 +1333,16 @@ namespace {
 
 // One workgroup per tile: gather the tile's sub-rows of all listed neurons,
 // accumulate into an LDS copy of the tile's ring, then add it into the ring.
+// Tiles are taken XCD by XCD (as in the step kernel), so that the sub-rows of
+// one neuron that neighbouring tiles read, and their entries, share lines in
+// one L2: taken in launch order, every XCD would fetch every line of a row.
 template <int SF>
 __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t *ids, int32_t count, int32_t id_offset,
                                                        int64_t n)
 {
     extern __shared__ int lds[];
     const DevNet &B = P.base;
-    const int t = blockIdx.x + P.tile_offset;         // tiles of one instance
+    const int t = xcd_tile(blockIdx.x, gridDim.x) + P.tile_offset;   // tiles of one instance, XCD by XCD
     const TileDesc td = P.tiles[t];
     const int l = threadIdx.x, nthr = blockDim.x;
     const int mask = B.ring_mask, R = mask + 1;
