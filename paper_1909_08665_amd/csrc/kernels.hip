@@ -544,11 +544,13 @@ __device__ __forceinline__ unsigned long long deliver_grouped(const void *__rest
 
 // Add the events of nb spikes, spike q's sub-row being records s_beg[q] ..
 // s_beg[q] + s_len[q] - 1, with groups of G lanes: group g (of nthr / G) takes
-// spikes g, g + groups, ..., and lane r of a group takes records r, r + G, ...
-// of each of them.  Each lane walks its (spike, record) items with a cursor
-// and keeps U records in flight, so there is neither a scan of the lengths
-// nor a search for an event's spike; the work is balanced when G is about the
-// mean sub-row length.  Returns the records this thread added.
+// spikes g, g + groups, ..., each in chunks of G consecutive records, lane r
+// of the group taking record r of the chunk.  The group's cursor (spike,
+// chunk) is the same in all its lanes, so each load instruction reads G
+// consecutive records per group (one or two cache lines), and each lane keeps
+// U records in flight; there is neither a scan of the lengths nor a search
+// for an event's spike.  Lanes past a sub-row's end idle for that chunk.
+// Returns the records this thread added.
 template <int SF, int U, class Add>
 __device__ __forceinline__ unsigned long long deliver_cursor(const void *__restrict__ syn, const int *s_beg,
                                                              const int *s_len, int nb, int G, Add add)
@@ -557,26 +559,30 @@ __device__ __forceinline__ unsigned long long deliver_cursor(const void *__restr
     int q = l / G;
     const int r = l - q * G;
     if (q >= groups) return 0;                         // lanes past the last whole group
-    int j = r, len = q < nb ? s_len[q] : 0;
-    while (q < nb && j >= len) {
-        q += groups;
-        len = q < nb ? s_len[q] : 0;
-    }
+    int j0 = 0, len = 0, beg = 0;
+    auto next_row = [&](int from) {                    // the group's next spike with records, from `from` on
+        for (q = from; q < nb; q += groups) {
+            len = s_len[q];
+            if (len > 0) {
+                beg = s_beg[q];
+                return;
+            }
+        }
+    };
+    next_row(q);
     unsigned long long done = 0;
     while (q < nb) {
         uint32_t idx[U];
         bool v[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            v[k] = q < nb;
-            idx[k] = v[k] ? static_cast<uint32_t>(s_beg[q] + j) : 0u;
-            if (v[k]) {
-                j += G;
-                while (j >= len) {                     // on to this group's next spike with a record r
-                    q += groups;
-                    if (q >= nb) break;
-                    len = s_len[q];
-                    j = r;
+            v[k] = q < nb && j0 + r < len;
+            idx[k] = v[k] ? static_cast<uint32_t>(beg + j0 + r) : 0u;
+            if (q < nb) {
+                j0 += G;
+                if (j0 >= len) {
+                    j0 = 0;
+                    next_row(q + groups);
                 }
             }
         }
