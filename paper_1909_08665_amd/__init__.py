@@ -7,9 +7,9 @@ The compute path is libmc.so (hand-written HIP kernels for gfx950 behind the
 C ABI in include/mc.h); this package is its Python binding.
 """
 from ._binding import (ENGINE_AUTO, ENGINE_GRAPH, ENGINE_TILED, EXPORTS, LIB_PATH, PROBE_DEVICE_ATOMICS,
-                       PROBE_HBM_COPY, PROBE_LDS_ATOMICS, MCError, Network, W_BF16, W_FP16, W_FP32, lib,
+                       PROBE_HBM_COPY, PROBE_HBM_GATHER, PROBE_LDS_ATOMICS, MCError, Network, W_BF16, W_FP16, W_FP32, lib,
                        make_config, probe)
 
 __all__ = ["Network", "MCError", "lib", "make_config", "LIB_PATH", "EXPORTS",
            "W_FP32", "W_FP16", "W_BF16", "ENGINE_AUTO", "ENGINE_GRAPH", "ENGINE_TILED", "probe",
-           "PROBE_HBM_COPY", "PROBE_LDS_ATOMICS", "PROBE_DEVICE_ATOMICS"]
+           "PROBE_HBM_COPY", "PROBE_HBM_GATHER", "PROBE_LDS_ATOMICS", "PROBE_DEVICE_ATOMICS"]

@@ -123,12 +123,12 @@ def lib():
     return L
 
 
-PROBE_HBM_COPY, PROBE_LDS_ATOMICS, PROBE_DEVICE_ATOMICS = 0, 1, 2
+PROBE_HBM_COPY, PROBE_LDS_ATOMICS, PROBE_DEVICE_ATOMICS, PROBE_HBM_GATHER = 0, 1, 2, 3
 
 
 def probe(kind, nbytes=0):
     """Memory-system ceiling on the current device: (rate, kernel ms); rate in
-    GB/s for PROBE_HBM_COPY, atomics/s for the atomic probes."""
+    GB/s for PROBE_HBM_COPY and PROBE_HBM_GATHER, atomics/s for the atomic probes."""
     rate, ms = C.c_double(), C.c_double()
     _check(lib().mc_probe(int(kind), int(nbytes), C.byref(rate), C.byref(ms)))
     return rate.value, ms.value

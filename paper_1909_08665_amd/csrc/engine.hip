@@ -1251,9 +1251,8 @@ int inject_run(mc_net *net, int32_t instance, const int32_t *ids, int64_t count,
     const int32_t off = net->host.inst_off[instance];
     HIP_TRY(hipMemcpyAsync(dev_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, net->stream));
     const mc::DevNet d = dev_view(net);
-    const size_t lds = mc::inject_lds_bytes(net->tile_max, net->host.ring);
     if (net->timing) HIP_TRY(hipEventRecord(net->ev0, net->stream));
-    if (net->engine == MC_ENGINE_TILED && lds + 256 <= 160 * 1024) {
+    if (net->engine == MC_ENGINE_TILED && mc::inject_batch(net->tile_max, net->host.ring) > 0) {
         mc::TiledNet tn{};
         tn.base = d;
         tn.n_tiles = net->n_tiles;
@@ -1694,7 +1693,7 @@ int mc_load_state(mc_net *net, const char *path)
 int mc_probe(int32_t kind, int64_t bytes, double *rate, double *kernel_ms)
 {
     if (!rate) return fail(MC_ERR_ARG, "rate must not be NULL");
-    if (kind < MC_PROBE_HBM_COPY || kind > MC_PROBE_DEVICE_ATOMICS) return fail(MC_ERR_ARG, "unknown probe");
+    if (kind < MC_PROBE_HBM_COPY || kind > MC_PROBE_HBM_GATHER) return fail(MC_ERR_ARG, "unknown probe");
     if (kind != MC_PROBE_LDS_ATOMICS && (bytes < 8192 || bytes > (int64_t{1} << 36)))
         return fail(MC_ERR_ARG, "bytes must be in [8 KiB, 64 GiB]");
     double ms = 0.0;

@@ -326,7 +326,8 @@ constexpr int kDeliverU = 4;                 // records in flight per thread in 
 constexpr int kCursorU = 8;                  // and with a cursor over many spikes
 constexpr int kRingBatch = 16;               // ring slots copied per round at launch start and end
 constexpr int kInjectU = 8;                  // and in the injection kernel
-constexpr int kInjBatch = 2048;              // spikes per batch of the injection kernel
+constexpr int kInjBatchMax = 8192;           // most spikes per batch of the injection kernel
+constexpr size_t kLdsBytes = 160 * 1024;     // LDS of one workgroup
 
 // Exclusive prefix sum of one value per thread, in thread order; returns the
 // exclusive prefix and writes the block total to *total.  s_wave: >= 17 ints.
@@ -1344,7 +1345,7 @@ namespace {
 // one L2: taken in launch order, every XCD would fetch every line of a row.
 template <int SF>
 __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t *ids, int32_t count, int32_t id_offset,
-                                                       int64_t n)
+                                                       int64_t n, int batch)
 {
     extern __shared__ int lds[];
     const DevNet &B = P.base;
@@ -1354,12 +1355,12 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     const int mask = B.ring_mask, R = mask + 1;
     const int tmax = P.tile_max, tlen = td.len;
     int *ring = lds;                                  // [R][tmax]
-    int *s_beg = ring + R * tmax;                     // [kInjBatch]
-    int *s_len = s_beg + kInjBatch;                   // [kInjBatch]
+    int *s_beg = ring + R * tmax;                     // [batch]
+    int *s_len = s_beg + batch;                       // [batch]
     for (int q = l; q < R * tmax; q += nthr) ring[q] = 0;
     __syncthreads();
-    for (int b0 = 0; b0 < count; b0 += kInjBatch) {
-        const int nb = min(kInjBatch, count - b0);
+    for (int b0 = 0; b0 < count; b0 += batch) {
+        const int nb = min(batch, count - b0);
         for (int q = l; q < nb; q += nthr) {
             const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(ids[b0 + q] + id_offset - td.inst_n0) * td.intiles];
             s_beg[q] = static_cast<int>(sr.x);
@@ -1409,9 +1410,17 @@ const void *inject_tiled_fn() { return reinterpret_cast<const void *>(&k_inject_
 
 }  // namespace
 
+int inject_batch(int tile_max, int ring)
+{
+    const size_t ring_bytes = sizeof(int) * (static_cast<size_t>(ring) * tile_max + 1) + 256;
+    if (ring_bytes >= kLdsBytes) return 0;
+    const size_t fit = (kLdsBytes - ring_bytes) / (2 * sizeof(int)) / 256 * 256;
+    return static_cast<int>(std::min<size_t>(kInjBatchMax, fit));
+}
+
 size_t inject_lds_bytes(int tile_max, int ring)
 {
-    return sizeof(int) * (static_cast<size_t>(ring) * tile_max + 2 * kInjBatch + 1);
+    return sizeof(int) * (static_cast<size_t>(ring) * tile_max + 2 * static_cast<size_t>(inject_batch(tile_max, ring)) + 1);
 }
 
 hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
@@ -1419,6 +1428,8 @@ hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, i
 {
     TiledNet arg = tn;
     arg.tile_offset = first_tile;
+    const int batch = inject_batch(tn.tile_max, tn.base.ring_mask + 1);
+    if (batch <= 0) return hipErrorInvalidValue;
     const size_t lds = inject_lds_bytes(tn.tile_max, tn.base.ring_mask + 1);
     const void *f = tn.syn_fmt == kSyn8F32 ? inject_tiled_fn<kSyn8F32>()
                   : tn.syn_fmt == kSyn8F16 ? inject_tiled_fn<kSyn8F16>()
@@ -1426,7 +1437,8 @@ hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, i
                   : tn.syn_fmt == kSyn4F16 ? inject_tiled_fn<kSyn4F16>() : inject_tiled_fn<kSyn4BF16>();
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    void *args[] = {&arg, const_cast<int32_t **>(&ids), &count, &id_offset, &n};
+    int batch_arg = batch;
+    void *args[] = {&arg, const_cast<int32_t **>(&ids), &count, &id_offset, &n, &batch_arg};
     return hipLaunchKernel(f, dim3(ntiles), dim3(threads), args, lds, st);
 }
 

@@ -165,7 +165,10 @@ TiledShape tiled_shape(int tile_max, int max_intiles, int ring, bool lds_ring, i
 hipError_t launch_tiled(const TiledNet &t, const TiledShape &sh, int64_t steps, bool coop, hipStream_t st);
 hipError_t tiled_max_coresident(int wfmt, const TiledShape &sh, int *blocks_per_cu);
 // Spike injection (external stimulation): deliver the rows of `ids` as if they
-// spiked in step n-1.  Tiled form needs the tile ring to fit in LDS.
+// spiked in step n-1.  Tiled form needs the tile ring to fit in LDS; it
+// takes the spikes in batches of inject_batch() (as many as fit in LDS beside
+// the staged ring, a multiple of 256; 0: the ring leaves no room for 256).
+int inject_batch(int tile_max, int ring);
 size_t inject_lds_bytes(int tile_max, int ring);
 // ids: device array of instance-local ids; id_offset: the instance's first global id.
 hipError_t launch_inject_tiled(const TiledNet &tn, int first_tile, int ntiles, int threads, const int32_t *ids,
@@ -183,9 +186,10 @@ hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, cons
 // of `bytes` (rate in GB/s of bytes read + written), kProbeLdsAtomics does LDS
 // int32 atomic adds at random addresses in every compute unit, and
 // kProbeDeviceAtomics does device-scope int32 atomic adds at random words of a
-// `bytes` buffer (rates in operations per second).  Each times its second
-// launch with HIP events.
-enum ProbeKind : int { kProbeHbmCopy = 0, kProbeLdsAtomics = 1, kProbeDeviceAtomics = 2 };
+// `bytes` buffer (rates in operations per second), and kProbeHbmGather reads
+// 64-byte chunks at random places of a `bytes` buffer (GB/s).  Each times its
+// second launch with HIP events.
+enum ProbeKind : int { kProbeHbmCopy = 0, kProbeLdsAtomics = 1, kProbeDeviceAtomics = 2, kProbeHbmGather = 3 };
 hipError_t run_probe(int kind, int64_t bytes, double *rate, double *kernel_ms);
 
 }  // namespace mc

@@ -66,6 +66,13 @@ def test_missing_table_and_bad_args_rejected():
     assert L.mc_set_step_budget(None, 5.0) == -1
     assert L.mc_set_launch(None, None) == -1
     assert L.mc_inject_spikes(None, 0, None, 0, None) == -1
+    # probes: unknown kind, buffer size out of range, no result pointer
+    rate, ms = C.c_double(), C.c_double()
+    assert L.mc_probe(4, 1 << 20, C.byref(rate), C.byref(ms)) == -1
+    assert L.mc_probe(-1, 1 << 20, C.byref(rate), C.byref(ms)) == -1
+    assert L.mc_probe(mc.PROBE_HBM_GATHER, 4096, C.byref(rate), C.byref(ms)) == -1
+    assert L.mc_probe(mc.PROBE_HBM_COPY, 1 << 37, C.byref(rate), C.byref(ms)) == -1
+    assert L.mc_probe(mc.PROBE_HBM_COPY, 1 << 20, None, None) == -1
     L.mc_free(None)
 
 
