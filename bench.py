@@ -173,8 +173,8 @@ def delivery_microbench(net, info, args, conn_desc):
     """Delivery of forced spike lists (S neurons spiking at once, ids spread over
     the populations in proportion to their sizes) through mc_inject_spikes:
     algorithmic bytes = events x bytes per synapse record + S x tiles x 8 B of
-    sub-row descriptors + the ring read-modify-write of the tiles, over the
-    HIP-event kernel time."""
+    sub-row descriptors + the read-modify-write of the ring cells that receive
+    events, over the HIP-event kernel time."""
     from synth_inputs import forced_spike_list
 
     import paper_1909_08665_amd as mc
@@ -201,7 +201,10 @@ def delivery_microbench(net, info, args, conn_desc):
         per = ms / launches
         ev = events / reps
         ptr_bytes = S * info["n_tiles"] * 8 if tiled else S * 16
-        ring_bytes = info["ring_depth"] * n * 8 if tiled else 0
+        # the staged ring's cells that received events, read and written back
+        # (expected distinct cells hit by ev events; exact for uniform slots)
+        cells = info["ring_depth"] * n
+        ring_bytes = 8 * cells * -np.expm1(-ev / cells) if tiled else 0
         algo = ev * b_event + ptr_bytes + ring_bytes
         gbs = algo / (per * 1e-3) / 1e9
         rows.append({"spikes": S, "events": int(ev), "kernel_ms": round(per, 4), "GB_s": round(gbs, 1),
@@ -440,25 +443,32 @@ def main():
     # 8-byte row pointer plus, in the tiled form, (T + 1) 4-byte sub-row
     # pointers of its instance's T tiles, and per neuron-step the state
     # traffic of the forms that keep it in HBM (graph: 26 B; tiled with the
-    # ring in global memory: 8 B, the slot read and clear) -- times the units
-    # one launch processes, over its HIP-event-timed duration.  The bytes of
-    # the store as actually laid out (packed records of syn_bytes, 8-byte
-    # sub-row entries) are reported beside them.
+    # ring in global memory: 8 B, the slot read and clear), and per launch of
+    # the tiled kernel the rings and neuron state it loads at its start and
+    # stores at its end (LDS ring: R x 4 B each way per neuron, a ring slice in
+    # global memory: twice that; state 9 B each way) -- times the units one
+    # launch processes, over its HIP-event-timed duration.  The bytes of the
+    # store as actually laid out (packed records of syn_bytes, 8-byte sub-row
+    # entries) are reported beside them.
     tiled = info["engine"] == mc.ENGINE_TILED
     b_event = 9 if args.wfmt == "fp32" else 7
     tiles_per_inst = info["n_tiles"] / n_inst if tiled else 0
     if tiled:
         per_spike = 8 + (tiles_per_inst + 1) * 4
         per_neuron_step = 0 if info["lds_ring"] else 8
+        per_neuron_launch = 2 * 9 + (2 if info["lds_ring"] else 4) * info["ring_depth"] * 4
         stored_per_spike = 8 * tiles_per_inst
         kname = "k_tiled (persistent step kernel)"
     else:
         per_spike = 8
         per_neuron_step = 26
+        per_neuron_launch = 0
         stored_per_spike = 16
         kname = "k_neuron + k_deliver (graph-captured step)"
-    algo_bytes = events * b_event + spikes * per_spike + args.steps * n_neurons * per_neuron_step
-    stored_bytes = events * info["syn_bytes"] + spikes * stored_per_spike + args.steps * n_neurons * per_neuron_step
+    launch_bytes = launches * n_neurons * per_neuron_launch
+    algo_bytes = events * b_event + spikes * per_spike + args.steps * n_neurons * per_neuron_step + launch_bytes
+    stored_bytes = (events * info["syn_bytes"] + spikes * stored_per_spike + args.steps * n_neurons * per_neuron_step
+                    + launch_bytes)
     avg_launch_ms = kernel_ms / max(1, launches)
     per_launch_s = max(1e-12, avg_launch_ms * 1e-3)
     achieved = algo_bytes / max(1, launches) / per_launch_s / 1e9 if kernel_ms > 0 else 0.0
