@@ -35,7 +35,7 @@ def build(verbose=False):
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
     jobs = [["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "netbuild.cpp"), "-o", os.path.join(BUILD, "netbuild.cpp.o")]]
-    for src in ("kernels.hip", "engine.hip", "devbuild.hip", "probe.hip"):
+    for src in ("kernels.hip", "engine.hip", "devbuild.hip", "probe.hip", "copyout.hip"):
         jobs.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
     objs = [j[-1] for j in jobs]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:

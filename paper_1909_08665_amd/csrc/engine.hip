@@ -52,6 +52,7 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 constexpr int64_t kSegMin = 100, kSegMax = 10000;   // steps between recorder drains
+constexpr int64_t kAbsorbSerial = 4096;             // records folded in on the calling thread alone
 // Tile words carry (n mod 32767) + 1: words left by earlier launches can be
 // taken for a new launch's only if the step index jumped ahead by about 2^15.
 constexpr int64_t kTagSafe = 32767 - kSegMax - 8;
@@ -129,6 +130,7 @@ struct mc_net {
     void *h_rblk[2] = {};
     uint64_t *rec[2] = {};            // entries of rblk[b]
     uint64_t *h_rec[2] = {};          // entries of h_rblk[b]
+    void *hd_rblk[2] = {};            // device addresses of h_rblk[b]
     int64_t rec_cap = 0;
     mc::StepCtl *h_ctl = nullptr;
     hipStream_t copy_stream = nullptr;
@@ -186,6 +188,7 @@ struct mc_net {
     int64_t step = 0;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;   // per instance
     std::vector<int64_t> inst_spikes, inst_events, inst_max_step;
+    std::vector<int32_t> absorb_scratch;            // per-step spike counts of a short record
     std::vector<int64_t> inst_dropped;  // events dropped by the step budget, per instance
     int64_t max_step_spikes = 0;
     int64_t steps_in_flight = 0;      // steps of the segment being drained
@@ -392,6 +395,7 @@ int upload(mc_net *nt, const mc_config *cfg, const std::vector<mc::SynSeg> *segs
         HIP_TRY(hipMemset(nt->rblk[b], 0, sizeof(mc::RecHead)));
         nt->rec[b] = reinterpret_cast<uint64_t *>(static_cast<char *>(nt->rblk[b]) + sizeof(mc::RecHead));
         nt->h_rec[b] = reinterpret_cast<uint64_t *>(static_cast<char *>(nt->h_rblk[b]) + sizeof(mc::RecHead));
+        HIP_TRY(hipHostGetDevicePointer(&nt->hd_rblk[b], nt->h_rblk[b], 0));
     }
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl), sizeof(mc::StepCtl), hipHostMallocDefault));
 
@@ -670,12 +674,39 @@ int absorb(mc_net *nt, int64_t total, uint32_t flags, const uint64_t *recs, int6
     const auto &meta = nt->host.meta;
     const int n_inst = nt->host.n_inst;
     span = std::max<int64_t>(1, span);
+    if (got < kAbsorbSerial) {
+        // A short record (a short run, or a segment at a low rate): one pass on
+        // this thread, each spike appended to its instance's list, with the
+        // per-step counts in scratch kept across calls.
+        std::vector<int32_t> &per = nt->absorb_scratch;
+        per.assign(static_cast<size_t>(span) * n_inst, 0);
+        for (int64_t q = 0; q < got; ++q) {
+            const int32_t gid = static_cast<int32_t>(static_cast<uint32_t>(recs[q]));
+            const int inst = n_inst == 1 ? 0 : static_cast<int>(meta[gid] >> 3);
+            const int64_t n = static_cast<int64_t>(recs[q] >> 32);
+            nt->unread[inst].emplace_back(n, gid - nt->host.inst_off[inst]);
+            nt->inst_spikes[inst] += 1;
+            nt->inst_events[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
+            const int64_t k = n - s0;
+            if (k >= 0 && k < span) per[static_cast<size_t>(k) * n_inst + inst] += 1;
+        }
+        for (int64_t k = 0; k < span; ++k) {
+            int64_t step_total = 0;
+            for (int j = 0; j < n_inst; ++j) {
+                const int64_t c = per[static_cast<size_t>(k) * n_inst + j];
+                step_total += c;
+                nt->inst_max_step[j] = std::max(nt->inst_max_step[j], c);
+            }
+            nt->max_step_spikes = std::max(nt->max_step_spikes, step_total);
+        }
+        if (total > nt->rec_cap || (flags & mc::kFlagRecordOverflow)) nt->overflow = true;
+        return MC_OK;
+    }
     // Threads take contiguous chunks of the record: a first pass counts spikes,
     // events and per-step spikes per instance, a second writes each spike into
     // its instance's list at the offset the counts give (order within a list
     // does not matter: mc_get_spikes sorts).
-    const int nth = got < (int64_t{1} << 12) ? 1
-                                           : static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    const int nth = static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
     struct Part {
         std::vector<int64_t> cnt, ev;
         std::vector<int32_t> per_step, per_inst_step;
@@ -878,9 +909,13 @@ int run_tiled(mc_net *nt, int64_t steps)
         if (timing) HIP_TRY(hipEventRecord(nt->seg_ev0[b], nt->stream));
         HIP_TRY(mc::launch_tiled(tn, nt->tiled_shape, seg, nt->coop, nt->stream));
         if (timing) HIP_TRY(hipEventRecord(nt->seg_ev1[b], nt->stream));
-        // one copy: the head and the first `guess` entries
-        HIP_TRY(hipMemcpyAsync(nt->h_rblk[b], nt->rblk[b], sizeof(mc::RecHead) + guess * sizeof(uint64_t),
-                               hipMemcpyDeviceToHost, nt->stream));
+        // the head and the first `guess` entries (at most as many as were
+        // recorded), written into the pinned buffer by a kernel of ours: it
+        // starts sooner after the step kernel than the runtime's copy does
+        HIP_TRY(mc::launch_copy_out(static_cast<const mc::RecHead *>(nt->rblk[b]), nt->rec[b], guess,
+                                    static_cast<mc::RecHead *>(nt->hd_rblk[b]),
+                                    reinterpret_cast<uint64_t *>(static_cast<char *>(nt->hd_rblk[b]) + sizeof(mc::RecHead)),
+                                    nt->stream));
         if (tn.budget_ticks)
             HIP_TRY(hipMemcpyAsync(nt->h_dropped + static_cast<size_t>(b) * T, tn.dropped, T * sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, nt->stream));

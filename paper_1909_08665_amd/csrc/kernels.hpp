@@ -177,6 +177,10 @@ hipError_t launch_inject_global(const DevNet &d, const int32_t *ids, int32_t cou
                                 hipStream_t st);
 // Device-side construction of the tiled engine's sub-row table and packed
 // synapse store (rows sorted by target; tile_of: tile index of every neuron).
+// Copy a recorder's head and first min(rec_total, n) entries into pinned host
+// memory (h_head, h_rec: device addresses of the pinned buffer).
+hipError_t launch_copy_out(const RecHead *head, const uint64_t *rec, int64_t n, RecHead *h_head, uint64_t *h_rec,
+                           hipStream_t st);
 hipError_t launch_subrows(const DevNet &d, const TileDesc *tiles_dev, int n_tiles, int64_t n_neurons, uint2 *subrow,
                           hipStream_t st);
 hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, const int32_t *tile_of, int64_t m,
