@@ -182,11 +182,12 @@ def delivery_microbench(net, info, args, conn_desc):
     b_event = info["syn_bytes"]
     tiled = info["engine"] == 2 and info["lds_ring"] == 1
     n = info["n_neurons"]
-    # the rate of 64-byte reads at random places of a buffer as large as the
-    # synapse store: what HBM gives this access shape, beside the streaming peak
+    # the rate of whole-line reads at random places of a buffer as large as the
+    # synapse store: what HBM gives reads at random places, beside the streaming
+    # copy
     gather_gbs = mc.probe(mc.PROBE_HBM_GATHER, 2 << 30)[0]
     copy_gbs = mc.probe(mc.PROBE_HBM_COPY, 2 << 30)[0]
-    log(f"D1 ceilings: random 64-byte gather {gather_gbs:.0f} GB/s, streaming copy {copy_gbs:.0f} GB/s")
+    log(f"D1 ceilings: random 128-byte line reads {gather_gbs:.0f} GB/s, streaming copy {copy_gbs:.0f} GB/s")
     rows = []
     for S in (25, 93, 1000, 4000, 20000, 77169):
         ids = forced_spike_list(S, args.scale, seed=S)
@@ -211,9 +212,9 @@ def delivery_microbench(net, info, args, conn_desc):
                      "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "frac_gather": round(gbs / gather_gbs, 4),
                      "events_per_s": round(ev / (per * 1e-3), 1)})
         log(f"D1 S={S:6d}: {ev:.3e} events in {per:.3f} ms -> {gbs:8.1f} GB/s ({gbs / HBM_PEAK_GBS:.1%} of HBM, "
-            f"{gbs / gather_gbs:.1%} of the gather rate), {ev / (per * 1e-3):.3e} events/s")
+            f"{gbs / gather_gbs:.1%} of the random-line rate), {ev / (per * 1e-3):.3e} events/s")
     return {"metric": "delivery microbenchmark (forced spike lists)", "unit": "GB/s", "dtype": "i32",
-            "data": "synthetic", "ceilings_GB_s": {"random_64B_gather": round(gather_gbs, 1),
+            "data": "synthetic", "ceilings_GB_s": {"random_line_reads": round(gather_gbs, 1),
                                                    "streaming_copy": round(copy_gbs, 1)},
             "config": {"workload": f"microcircuit scale {args.scale}, {args.wfmt.upper()} store, "
                                             f"{'tiled LDS-staged' if tiled else 'global-atomic'} delivery",

@@ -395,9 +395,10 @@ int mc_set_wait_limit(struct mc_net *net, int64_t polls);
  *   MC_PROBE_DEVICE_ATOMICS device-scope int32 atomic adds at random words of a
  *                           `bytes` buffer (L2-, Infinity-Cache- or HBM-resident
  *                           by size; the global-ring and graph forms): atomics/s;
- *   MC_PROBE_HBM_GATHER     reads of 64 contiguous bytes at random 64-byte
- *                           aligned places of a `bytes` buffer, by groups of 8
- *                           lanes (the shape of a spike's sub-row read): GB/s.
+ *   MC_PROBE_HBM_GATHER     reads of whole 128-byte cache lines at random
+ *                           places of a `bytes` buffer, by groups of 16 lanes
+ *                           (the unit in which sub-row reads at random places
+ *                           reach HBM): GB/s.
  * *kernel_ms (may be NULL) receives the timed launch's duration.  Allocates and
  * frees its own device buffers.  Errors: MC_ERR_ARG (unknown kind, bytes outside
  * [8 KiB, 64 GiB]), MC_ERR_NOMEM, MC_ERR_HIP.

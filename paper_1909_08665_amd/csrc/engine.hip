@@ -545,7 +545,8 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     nt->xent_high = 0;
     {
         const size_t rec = sf <= mc::kSyn8BF16 ? 8 : 4;
-        hipError_t e = hipMalloc(&nt->syn, std::max<size_t>(1, static_cast<size_t>(nt->host.m) * rec));
+        // at least 16 bytes: idle lanes of the pipelined injection read record 0
+        hipError_t e = hipMalloc(&nt->syn, std::max<size_t>(16, static_cast<size_t>(nt->host.m) * rec));
         if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
     const mc::DevNet d = dev_view(nt);

@@ -478,6 +478,39 @@ __device__ __forceinline__ int syn_record(const void *__restrict__ syn, uint32_t
     return __float2int_rn(f * 256.0f);
 }
 
+// The same record in two halves, so that its load can be issued well before it
+// is decoded: the raw bits (8 or 4 bytes, widened), then the decoding.
+template <int SF>
+__device__ __forceinline__ uint64_t rec_load(const void *__restrict__ syn, uint32_t j)
+{
+    if constexpr (SF <= kSyn8BF16) {
+        const uint2 r = static_cast<const uint2 *>(syn)[j];
+        return (static_cast<uint64_t>(r.y) << 32) | r.x;
+    } else {
+        return static_cast<const uint32_t *>(syn)[j];
+    }
+}
+template <int SF>
+__device__ __forceinline__ int rec_decode(uint64_t raw, int &local, int &d)
+{
+    float f;
+    if constexpr (SF <= kSyn8BF16) {
+        const uint32_t x = static_cast<uint32_t>(raw), y = static_cast<uint32_t>(raw >> 32);
+        local = static_cast<int>(x & 0xFFFFu);
+        d = static_cast<int>((x >> 16) & 0xFFu);
+        if constexpr (SF == kSyn8F32) f = __uint_as_float(y);
+        else if constexpr (SF == kSyn8F16) f = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(y)));
+        else f = __uint_as_float(y << 16);
+    } else {
+        const uint32_t r = static_cast<uint32_t>(raw);
+        local = static_cast<int>(r & 0x3FFu);
+        d = static_cast<int>((r >> 10) & 0x3Fu);
+        if constexpr (SF == kSyn4F16) f = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(r >> 16)));
+        else f = __uint_as_float(r & 0xFFFF0000u);
+    }
+    return __float2int_rn(f * 256.0f);
+}
+
 // Add the events of nb spikes into a ring: spike q's sub-row is records
 // s_beg[q] .. s_beg[q] + len - 1, s_pre the exclusive prefix of the lengths
 // (s_pre[nb] = E), so event e belongs to the last q with s_pre[q] <= e.
@@ -597,6 +630,76 @@ __device__ __forceinline__ unsigned long long deliver_cursor(const void *__restr
                 add(tg[k], d[k], wq[k]);
                 ++done;
             }
+    }
+    return done;
+}
+
+// deliver_cursor with two sets of U records: the loads of the next round are
+// issued before the current round is decoded and added, so the memory system
+// always has a round in flight (for long spike lists, where the rounds of one
+// lane are many).  Same lane-group cursor, same records, same adds.
+template <int SF, int U, class Add>
+__device__ __forceinline__ unsigned long long deliver_cursor_pipelined(const void *__restrict__ syn, const int *s_beg,
+                                                                       const int *s_len, int nb, int G, Add add)
+{
+    const int l = threadIdx.x, groups = static_cast<int>(blockDim.x) / G;
+    int q = l / G;
+    const int r = l - q * G;
+    if (q >= groups) return 0;                         // lanes past the last whole group
+    int j0 = 0, len = 0, beg = 0;
+    auto next_row = [&](int from) {
+        for (q = from; q < nb; q += groups) {
+            len = s_len[q];
+            if (len > 0) {
+                beg = s_beg[q];
+                return;
+            }
+        }
+    };
+    // the cursor's next U records: issue their loads (every lane issues all U,
+    // idle ones reading record 0, so that the loads form one straight run and
+    // the wait before a round's adds covers only that round's loads)
+    auto fill = [&](uint64_t (&raw)[U], bool (&v)[U]) {
+        uint32_t idx[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            v[k] = q < nb && j0 + r < len;
+            idx[k] = v[k] ? static_cast<uint32_t>(beg + j0 + r) : 0u;
+            if (q < nb) {
+                j0 += G;
+                if (j0 >= len) {
+                    j0 = 0;
+                    next_row(q + groups);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) raw[k] = rec_load<SF>(syn, idx[k]);
+    };
+    unsigned long long done = 0;
+    auto consume = [&](const uint64_t (&raw)[U], const bool (&v)[U]) {
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (v[k]) {
+                int tg, d;
+                const int wq = rec_decode<SF>(raw[k], tg, d);
+                add(tg, d, wq);
+                ++done;
+            }
+    };
+    next_row(q);
+    uint64_t ra[U], rb[U];
+    bool va[U], vb[U];
+    fill(ra, va);
+    for (;;) {
+        bool more = q < nb;
+        fill(rb, vb);
+        consume(ra, va);
+        if (!more) break;
+        more = q < nb;
+        fill(ra, va);
+        consume(rb, vb);
+        if (!more) break;
     }
     return done;
 }
@@ -1367,7 +1470,7 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
             s_len[q] = static_cast<int>(sr.y);
         }
         __syncthreads();
-        deliver_cursor<SF, kInjectU>(P.syn, s_beg, s_len, nb, P.lanes, [&](int tg, int d, int wq) {
+        deliver_cursor_pipelined<SF, kInjectU>(P.syn, s_beg, s_len, nb, P.lanes, [&](int tg, int d, int wq) {
             atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, wq);
         });
         __syncthreads();

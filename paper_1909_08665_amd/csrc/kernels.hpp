@@ -191,7 +191,7 @@ hipError_t launch_pack_synapses(const DevNet &d, const TileDesc *tiles_dev, cons
 // int32 atomic adds at random addresses in every compute unit, and
 // kProbeDeviceAtomics does device-scope int32 atomic adds at random words of a
 // `bytes` buffer (rates in operations per second), and kProbeHbmGather reads
-// 64-byte chunks at random places of a `bytes` buffer (GB/s).  Each times its
+// whole 128-byte lines at random places of a `bytes` buffer (GB/s).  Each times its
 // second launch with HIP events.
 enum ProbeKind : int { kProbeHbmCopy = 0, kProbeLdsAtomics = 1, kProbeDeviceAtomics = 2, kProbeHbmGather = 3 };
 hipError_t run_probe(int kind, int64_t bytes, double *rate, double *kernel_ms);

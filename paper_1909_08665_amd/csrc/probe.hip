@@ -3,9 +3,9 @@
 // integer atomics (the tiled engine's ring updates) and the rate of device
 // integer atomics on random targets in a buffer of a chosen size (resident in
 // L2, in the Infinity Cache, or spread over HBM: the global-ring variants and
-// the graph engine's delivery), and the rate of 64-byte reads at random places
-// of a large buffer (the shape of the tiled delivery's sub-row reads, which no
-// streaming copy shows).  Each probe times its kernel with HIP events
+// the graph engine's delivery), and the rate of whole cache-line reads at
+// random places of a large buffer (what sub-row reads at random places cost
+// HBM, which no streaming copy shows).  Each probe times its kernel with HIP events
 // on a stream of its own and returns the rate.
 #include <hip/hip_runtime.h>
 
@@ -65,17 +65,18 @@ __global__ __launch_bounds__(256) void k_probe_global_atomics(uint32_t *buf, uin
     }
 }
 
-// Gather: lanes in groups of 8 read 64 contiguous bytes (8 bytes each) at
-// random 64-byte aligned places of a buffer of mask + 1 such chunks -- the
-// shape of the delivery's sub-row reads -- 8 reads in flight per lane, for
-// `rounds` rounds; the xor of what a thread read is stored, so that no read
-// can be dropped.
+// Gather: lanes in groups of 16 read one 128-byte cache line (8 bytes each)
+// at random line-aligned places of a buffer of mask + 1 lines -- the unit in
+// which a sub-row read at a random place reaches HBM (every L2 miss fetches a
+// whole line) -- 8 reads in flight per lane, for `rounds` rounds; the xor of
+// what a thread read is stored, so that no read can be dropped.
 constexpr int kGatherU = 8;
+constexpr int kGatherLanes = 16;
 __global__ __launch_bounds__(kProbeThreads) void k_probe_gather(const uint2 *__restrict__ buf, uint64_t mask,
                                                                 uint32_t rounds, uint2 *out)
 {
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t r = id & 7u, g = id >> 3;          // the group's lanes draw the same places
+    const uint32_t r = id % kGatherLanes, g = id / kGatherLanes;   // the group's lanes draw the same places
     uint32_t x = mix(g + 1), y = mix(g ^ 0x9e3779b9U);
     uint2 acc = make_uint2(0u, 0u);
     for (uint32_t i = 0; i < rounds; ++i) {
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_gather(const uint2 *__r
             x = lcg(x);
             y = lcg(y);
             const uint64_t c = ((static_cast<uint64_t>(x) << 32) | y) & mask;
-            v[k] = buf[c * 8 + r];
+            v[k] = buf[c * kGatherLanes + r];
         }
 #pragma unroll
         for (int k = 0; k < kGatherU; ++k) {
@@ -157,11 +158,11 @@ hipError_t run_probe(int kind, int64_t bytes, double *rate, double *kernel_ms)
                     err = hipErrorUnknown;
             }
         } else if (kind == kProbeHbmGather) {
-            uint64_t chunks = 128;                                          // 64-byte chunks, a power of two
-            while (chunks * 2 * 64 <= static_cast<uint64_t>(bytes)) chunks *= 2;
+            uint64_t chunks = 64;                                           // 128-byte lines, a power of two
+            while (chunks * 2 * 128 <= static_cast<uint64_t>(bytes)) chunks *= 2;
             const int grid = cus * 2;                                       // two 1024-thread workgroups per CU
             const uint32_t rounds = 64;
-            if (ok(hipMalloc(&a, chunks * 64)) && ok(hipMemsetAsync(a, 3, chunks * 64, st)) &&
+            if (ok(hipMalloc(&a, chunks * 128)) && ok(hipMemsetAsync(a, 3, chunks * 128, st)) &&
                 ok(hipMalloc(&b, static_cast<size_t>(grid) * kProbeThreads * sizeof(uint2)))) {
                 for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
                     ok(hipEventRecord(e0, st));
