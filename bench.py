@@ -487,12 +487,18 @@ def main():
                                   if kernel_ms > 0 else 0.0},
                 "workload_key": workload_key}
     # Atomic throughput: every recurrent event is one int32 atomic add into a
-    # ring slot -- LDS atomics when the tile rings sit in LDS, device atomics
-    # otherwise -- against the ceiling the probe measures on this device.
+    # ring slot -- LDS atomics when the tile rings sit in LDS; with the ring in
+    # each workgroup's global slice, LDS atomics for the delays the LDS window
+    # holds and workgroup-scope atomics into the slice for the others (the LDS
+    # rate is then the ceiling: no form of the add is faster); device atomics in
+    # the graph engine -- against the ceiling the probe measures on this device.
     atomics = None
     if kernel_ms > 0:
         if tiled and info["lds_ring"]:
             peak, akind = mc.probe(mc.PROBE_LDS_ATOMICS)[0], "LDS int32 atomic add (random words)"
+        elif tiled:
+            peak, akind = mc.probe(mc.PROBE_LDS_ATOMICS)[0], \
+                "LDS (window) and workgroup-scope int32 atomic adds; peak: the LDS atomic rate"
         else:
             ring_bytes = info["ring_depth"] * n_neurons * 4
             peak, akind = mc.probe(mc.PROBE_DEVICE_ATOMICS, max(8192, ring_bytes))[0], \
