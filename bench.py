@@ -222,6 +222,30 @@ def delivery_microbench(net, info, args, conn_desc):
             "rows": rows}
 
 
+def probe_table():
+    """Every ceiling mc_probe measures, at buffer sizes that sit in one XCD's
+    L2 (1 MiB), in the Infinity Cache (64 MiB) and in HBM (2 GiB)."""
+    import torch
+
+    import paper_1909_08665_amd as mc
+
+    out = {"metric": "memory-system ceilings (mc_probe)", "device": torch.cuda.get_device_name(0), "rows": []}
+    rows = [("streaming copy, read + written", mc.PROBE_HBM_COPY, 2 << 30, "GB/s"),
+            ("whole 128-byte lines at random places", mc.PROBE_HBM_GATHER, 2 << 30, "GB/s"),
+            ("whole 128-byte lines at random places", mc.PROBE_HBM_GATHER, 64 << 20, "GB/s"),
+            ("whole 128-byte lines at random places", mc.PROBE_HBM_GATHER, 1 << 20, "GB/s"),
+            ("LDS int32 atomic add, random words", mc.PROBE_LDS_ATOMICS, 0, "atomics/s"),
+            ("device int32 atomic add, random words", mc.PROBE_DEVICE_ATOMICS, 1 << 20, "atomics/s"),
+            ("device int32 atomic add, random words", mc.PROBE_DEVICE_ATOMICS, 64 << 20, "atomics/s"),
+            ("device int32 atomic add, random words", mc.PROBE_DEVICE_ATOMICS, 2 << 30, "atomics/s")]
+    for name, kind, nbytes, unit in rows:
+        rate, ms = mc.probe(kind, nbytes)
+        out["rows"].append({"probe": name, "bytes": nbytes, "rate": round(rate, 1), "unit": unit,
+                            "kernel_ms": round(ms, 4)})
+        log(f"{name:40s} {nbytes / 2**20:8.0f} MiB: {rate:.4g} {unit} ({ms:.3f} ms)")
+    return out
+
+
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_08665_amd", "csrc", "kernels.hip")
 
@@ -342,6 +366,8 @@ def main():
                     help="oracle steps timed on one thread after the multi-thread sample (0: none)")
     ap.add_argument("--d1", action="store_true",
                     help="delivery microbenchmark: inject forced spike lists of 25..77169 neurons")
+    ap.add_argument("--probes", action="store_true",
+                    help="only print the memory-system ceilings mc_probe measures on this device and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device twice (reference for HBM byte counters) and exit")
     ap.add_argument("--stability", type=float, default=0, metavar="HOURS",
@@ -369,6 +395,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.probes:
+        print(json.dumps(probe_table()), flush=True)
+        return
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
