@@ -164,10 +164,11 @@ typedef struct mc_launch {
                                     Speed only: results do not depend on it. */
     int32_t coop;                /* TILED engine: 1 cooperative launch (the runtime guarantees
                                     that all workgroups are resident at once), 2 ordinary
-                                    launch (the default: 15-20 us cheaper per launch; relies on
-                                    the occupancy check made at set-up, and on no other work
+                                    launch (the default: 15-20 us cheaper per launch) while the
+                                    tiles are at most one per compute unit -- with more, the
+                                    launch is cooperative either way; relies on no other work
                                     holding the compute units for longer than the wait limit
-                                    of mc_set_wait_limit).  Speed only. */
+                                    of mc_set_wait_limit.  Speed only. */
     int32_t lanes;               /* TILED engine: lanes per spike when a step's (or an injection's)
                                     spikes are delivered by a cursor, 1..64 (default: about the
                                     mean sub-row length).  Speed only. */
@@ -299,9 +300,12 @@ int mc_inject_spikes_noalloc(struct mc_net *net, int32_t instance, const int32_t
 int mc_set_launch(struct mc_net *net, const mc_launch *l);
 
 /*
- * Autotuner: time each candidate launch configuration for `trial_steps` steps on
- * a saved copy of the state, restore the state, and keep the fastest.  Results of
- * later runs do not depend on the choice.
+ * Autotuner: time each candidate launch configuration (the one in use first)
+ * twice for `trial_steps` steps on a saved copy of the state, restore the state,
+ * and keep the fastest; another configuration replaces the one in use only when
+ * at least 3 % faster.  Results of later runs do not depend on the choice.
+ * Errors: MC_ERR_ARG (trial_steps outside [1, 100000]), MC_ERR_HIP (a trial
+ * failed: the configuration and state from before the call are restored).
  */
 int mc_tune(struct mc_net *net, int64_t trial_steps);
 

@@ -327,7 +327,12 @@ constexpr int kCursorU = 8;                  // and with a cursor over many spik
 constexpr int kRingBatch = 16;               // ring slots copied per round at launch start and end
 constexpr int kInjectU = 8;                  // and in the injection kernel
 constexpr int kInjBatchMax = 8192;           // most spikes per batch of the injection kernel
-constexpr size_t kLdsBytes = 160 * 1024;     // LDS of one workgroup
+constexpr size_t kLdsBytes = 160 * 1024;     // LDS of a compute unit (and the most one workgroup may use)
+// LDS counted per workgroup in blocks of this size when bounding the
+// workgroups a compute unit holds: larger than the allocation granularity, as
+// a margin (three workgroups of 54.2 KB, 162.6 KB of the 160 KB, were not all
+// placed; two of 65 KB and one of 102 KB are)
+constexpr size_t kLdsBlock = 2048;
 
 // Exclusive prefix sum of one value per thread, in thread order; returns the
 // exclusive prefix and writes the block total to *total.  s_wave: >= 17 ints.
@@ -1394,6 +1399,15 @@ hipError_t tiled_max_coresident(int syn_fmt, const TiledShape &sh, int *blocks_p
         int b = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, sh.threads, sh.lds);
         if (e != hipSuccess) return e;
+        // The occupancy query can count more workgroups per compute unit than
+        // their LDS (static + dynamic) leaves room for; a tiling that relied
+        // on it would wait for workgroups that are never placed.  Bound it by
+        // the LDS directly.
+        hipFuncAttributes a{};
+        e = hipFuncGetAttributes(&a, f);
+        if (e != hipSuccess) return e;
+        const size_t per = (sh.lds + a.sharedSizeBytes + kLdsBlock - 1) / kLdsBlock * kLdsBlock;
+        b = std::min(b, static_cast<int>(kLdsBytes / per));
         *blocks_per_cu = std::min(*blocks_per_cu, b);
     }
     return hipSuccess;

@@ -143,6 +143,39 @@ def test_launch_configuration_invariance(conn, knobs):
     assert _same_run(net, orc) > 100
 
 
+def test_more_tiles_than_compute_units(conn):
+    """Tiles of 16 neurons at 10 % scale: 483 workgroups, two or more per
+    compute unit, which the library then launches cooperatively so that all of
+    them are resident at once; bit-exact against the oracle."""
+    _say("more tiles than compute units")
+    net = mc.Network.build(16, 0.1, conn)
+    net.set_launch(engine=mc.ENGINE_TILED, tile=16)
+    info = net.info()
+    assert info["n_tiles"] > 256, info
+    orc = _oracle(16, 0.1, conn)
+    for chunk in (7, 993):
+        net.run(chunk)
+        orc.run(chunk)
+    assert _same_run(net, orc) > 100
+
+
+def test_tiling_beyond_lds_residency_is_refused(conn):
+    """Full scale in tiles of 101 neurons: 765 workgroups of about 54 KB of LDS
+    each, of which only two fit in a compute unit's 160 KB, so they cannot all
+    be resident at once.  The tiling is refused at set-up (the occupancy
+    query alone would have let it through, and the launch would then wait for
+    workgroups that are never placed); 151-neuron tiles, two per CU, run."""
+    _say("tiling beyond LDS residency")
+    net = mc.Network.build(1, 1.0, conn)
+    with pytest.raises(mc.MCError) as e:
+        net.set_launch(engine=mc.ENGINE_TILED, tile=101, ring=1)
+    assert e.value.code == -9 and "resident" in str(e.value)
+    net.set_launch(engine=mc.ENGINE_TILED, tile=151, ring=1)
+    assert net.info()["n_tiles"] == 512
+    net.run(50)
+    assert len(net.spikes()[0]) > 0
+
+
 def test_tile_too_large_for_lds_is_refused(conn):
     _say("tile refusal")
     net = mc.Network.build(12, 0.05, conn)
