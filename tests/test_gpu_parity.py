@@ -143,6 +143,27 @@ def test_launch_configuration_invariance(conn, knobs):
     assert _same_run(net, orc) > 100
 
 
+def test_recorder_larger_than_first_copy(conn):
+    """Every neuron of a 10 % network starts above threshold: the first step
+    records all 7,718 spikes, more than the entries the step kernel's launch
+    has copied to the host with its head (sized from the spike rate so far,
+    4,160 here), so the host copies the rest; the raster is still the
+    oracle's, bit for bit."""
+    _say("recorder larger than the first copy")
+    net = mc.Network.build(17, 0.1, conn)
+    orc = _oracle(17, 0.1, conn)
+    u, _, _ = orc.state()
+    u[:] = 16.0
+    orc.set_state(u=u)
+    net.set_state(u=u.astype(np.float32))
+    net.run(1)
+    orc.run(1)
+    assert _same_run(net, orc) == len(u)
+    net.run(300)
+    orc.run(300)
+    assert _same_run(net, orc) > 0
+
+
 def test_more_tiles_than_compute_units(conn):
     """Tiles of 16 neurons at 10 % scale: 483 workgroups, two or more per
     compute unit, which the library then launches cooperatively so that all of
