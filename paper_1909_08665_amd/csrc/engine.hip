@@ -546,8 +546,10 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     nt->xent_high = 0;
     {
         const size_t rec = sf <= mc::kSyn8BF16 ? 8 : 4;
-        // at least 16 bytes: idle lanes of the pipelined injection read record 0
-        hipError_t e = hipMalloc(&nt->syn, std::max<size_t>(16, static_cast<size_t>(nt->host.m) * rec));
+        // a whole number of 16-byte chunks, at least one: the injection reads the
+        // store in aligned 16-byte chunks, idle lanes reading the first
+        const size_t bytes = std::max<size_t>(16, (static_cast<size_t>(nt->host.m) * rec + 15) / 16 * 16);
+        hipError_t e = hipMalloc(&nt->syn, bytes);
         if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
     const mc::DevNet d = dev_view(nt);
@@ -565,7 +567,6 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
         if (e != hipSuccess) return fail(MC_ERR_HIP, std::string("tiled store build: ") + hipGetErrorString(e));
     }
     nt->syn_fmt = sf;
-    // lanes per spike for cursor delivery: about the mean sub-row length
     // lanes per spike for cursor delivery: half the mean sub-row length (two or
     // more records per lane keep more loads in flight; measured at full scale:
     // 8 lanes deliver 16 % more events per second than 16, 2x more than 32)

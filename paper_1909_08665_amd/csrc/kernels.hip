@@ -325,8 +325,9 @@ constexpr int kWordIds = 3;                  // spike offsets carried by a tile'
 constexpr int kDeliverU = 4;                 // records in flight per thread in the step kernel's delivery
 constexpr int kCursorU = 8;                  // and with a cursor over many spikes
 constexpr int kRingBatch = 16;               // ring slots copied per round at launch start and end
-constexpr int kInjectU = 8;                  // and in the injection kernel
+constexpr int kInjectU = 4;                  // and in the injection kernel (16-byte chunks)
 constexpr int kInjBatchMax = 8192;           // most spikes per batch of the injection kernel
+constexpr int kInjWriteBack = 10;            // ring cells per thread in flight in the injection's write-back
 constexpr size_t kLdsBytes = 160 * 1024;     // LDS of a compute unit (and the most one workgroup may use)
 // LDS counted per workgroup in blocks of this size when bounding the
 // workgroups a compute unit holds: larger than the allocation granularity, as
@@ -483,18 +484,8 @@ __device__ __forceinline__ int syn_record(const void *__restrict__ syn, uint32_t
     return __float2int_rn(f * 256.0f);
 }
 
-// The same record in two halves, so that its load can be issued well before it
-// is decoded: the raw bits (8 or 4 bytes, widened), then the decoding.
-template <int SF>
-__device__ __forceinline__ uint64_t rec_load(const void *__restrict__ syn, uint32_t j)
-{
-    if constexpr (SF <= kSyn8BF16) {
-        const uint2 r = static_cast<const uint2 *>(syn)[j];
-        return (static_cast<uint64_t>(r.y) << 32) | r.x;
-    } else {
-        return static_cast<const uint32_t *>(syn)[j];
-    }
-}
+// Decode a record from its raw bits (8 or 4 bytes, widened), loaded apart
+// from its decoding so that the load can be issued well before.
 template <int SF>
 __device__ __forceinline__ int rec_decode(uint64_t raw, int &local, int &d)
 {
@@ -639,71 +630,98 @@ __device__ __forceinline__ unsigned long long deliver_cursor(const void *__restr
     return done;
 }
 
-// deliver_cursor with two sets of U records: the loads of the next round are
-// issued before the current round is decoded and added, so the memory system
-// always has a round in flight (for long spike lists, where the rounds of one
-// lane are many).  Same lane-group cursor, same records, same adds.
+// The lane-group cursor of deliver_cursor for long spike lists, reading the
+// store in aligned 16-byte chunks (two 8-byte or four 4-byte records): lane r
+// of a group takes chunk j0 + r of the spike's sub-row, so that a group's load
+// covers G x 16 consecutive bytes, and a round of U chunks per lane needs half
+// (or a quarter) of the loads and cursor steps of one record per load.  A chunk
+// at either end of a sub-row also holds records of the neighbouring sub-rows: a
+// per-chunk mask keeps only the spike's own.  Two sets of U chunks: the loads
+// of the next round are issued before the current round is decoded and added,
+// so the memory system always has a round in flight.  The store must be
+// allocated to a whole number of 16-byte chunks.  s_row[q] = (first record,
+// length) of spike q's sub-row, read as one word.  Returns the records this
+// thread added.
 template <int SF, int U, class Add>
-__device__ __forceinline__ unsigned long long deliver_cursor_pipelined(const void *__restrict__ syn, const int *s_beg,
-                                                                       const int *s_len, int nb, int G, Add add)
+__device__ __forceinline__ unsigned long long deliver_chunks_pipelined(const void *__restrict__ syn, const int2 *s_row,
+                                                                       int nb, int G, Add add)
 {
+    constexpr int P = SF <= kSyn8BF16 ? 2 : 4;         // records per chunk
     const int l = threadIdx.x, groups = static_cast<int>(blockDim.x) / G;
     int q = l / G;
     const int r = l - q * G;
-    if (q >= groups) return 0;                         // lanes past the last whole group
-    int j0 = 0, len = 0, beg = 0;
+    if (q >= groups) return 0;
+    int j0 = 0, lo = 0, hi = 0, c0 = 0, nch = 0;       // sub-row [lo, hi): chunks c0 .. c0 + nch - 1
     auto next_row = [&](int from) {
         for (q = from; q < nb; q += groups) {
-            len = s_len[q];
-            if (len > 0) {
-                beg = s_beg[q];
+            const int2 row = s_row[q];
+            if (row.y > 0) {
+                lo = row.x;
+                hi = lo + row.y;
+                c0 = lo / P;
+                nch = (hi - 1) / P + 1 - c0;
                 return;
             }
         }
     };
-    // the cursor's next U records: issue their loads (every lane issues all U,
-    // idle ones reading record 0, so that the loads form one straight run and
-    // the wait before a round's adds covers only that round's loads)
-    auto fill = [&](uint64_t (&raw)[U], bool (&v)[U]) {
+    const uint4 *chunks = static_cast<const uint4 *>(syn);
+    // the cursor's next U chunks: their loads, and the mask of the records of
+    // each that belong to its spike (0 for an idle lane, which reads chunk 0)
+    auto fill = [&](uint4 (&raw)[U], int (&m)[U]) {
         uint32_t idx[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            v[k] = q < nb && j0 + r < len;
-            idx[k] = v[k] ? static_cast<uint32_t>(beg + j0 + r) : 0u;
+            m[k] = 0;
+            idx[k] = 0u;
             if (q < nb) {
+                if (j0 + r < nch) {
+                    const int c = c0 + j0 + r, first = max(lo - c * P, 0), last = min(hi - c * P, P);
+                    m[k] = ((1 << last) - 1) & ~((1 << first) - 1);
+                    idx[k] = static_cast<uint32_t>(c);
+                }
                 j0 += G;
-                if (j0 >= len) {
+                if (j0 >= nch) {
                     j0 = 0;
                     next_row(q + groups);
                 }
             }
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) raw[k] = rec_load<SF>(syn, idx[k]);
+        for (int k = 0; k < U; ++k) raw[k] = chunks[idx[k]];
     };
     unsigned long long done = 0;
-    auto consume = [&](const uint64_t (&raw)[U], const bool (&v)[U]) {
+    auto one = [&](uint64_t rec) {
+        int tg, d;
+        const int wq = rec_decode<SF>(rec, tg, d);
+        add(tg, d, wq);
+        ++done;
+    };
+    auto consume = [&](const uint4 (&raw)[U], const int (&m)[U]) {
 #pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (v[k]) {
-                int tg, d;
-                const int wq = rec_decode<SF>(raw[k], tg, d);
-                add(tg, d, wq);
-                ++done;
+        for (int k = 0; k < U; ++k) {
+            if constexpr (P == 2) {
+                if (m[k] & 1) one((static_cast<uint64_t>(raw[k].y) << 32) | raw[k].x);
+                if (m[k] & 2) one((static_cast<uint64_t>(raw[k].w) << 32) | raw[k].z);
+            } else {
+                if (m[k] & 1) one(raw[k].x);
+                if (m[k] & 2) one(raw[k].y);
+                if (m[k] & 4) one(raw[k].z);
+                if (m[k] & 8) one(raw[k].w);
             }
+        }
     };
     next_row(q);
-    uint64_t ra[U], rb[U];
-    bool va[U], vb[U];
-    fill(ra, va);
+    uint4 ra[U], rb[U];
+    int ma[U], mb[U];
+    fill(ra, ma);
     for (;;) {
         bool more = q < nb;
-        fill(rb, vb);
-        consume(ra, va);
+        fill(rb, mb);
+        consume(ra, ma);
         if (!more) break;
         more = q < nb;
-        fill(ra, va);
-        consume(rb, vb);
+        fill(ra, ma);
+        consume(rb, mb);
         if (!more) break;
     }
     return done;
@@ -1472,36 +1490,47 @@ __global__ __launch_bounds__(1024) void k_inject_tiled(TiledNet P, const int32_t
     const int mask = B.ring_mask, R = mask + 1;
     const int tmax = P.tile_max, tlen = td.len;
     int *ring = lds;                                  // [R][tmax]
-    int *s_beg = ring + R * tmax;                     // [batch]
-    int *s_len = s_beg + batch;                       // [batch]
+    // [batch] (first record, length) of each spike's sub-row, 8-byte aligned
+    int2 *s_row = reinterpret_cast<int2 *>(ring + ((R * tmax + 1) & ~1));
     for (int q = l; q < R * tmax; q += nthr) ring[q] = 0;
     __syncthreads();
     for (int b0 = 0; b0 < count; b0 += batch) {
         const int nb = min(batch, count - b0);
         for (int q = l; q < nb; q += nthr) {
             const uint2 sr = P.subrow[td.sub_base + static_cast<int64_t>(ids[b0 + q] + id_offset - td.inst_n0) * td.intiles];
-            s_beg[q] = static_cast<int>(sr.x);
-            s_len[q] = static_cast<int>(sr.y);
+            s_row[q] = make_int2(static_cast<int>(sr.x), static_cast<int>(sr.y));
         }
         __syncthreads();
-        deliver_cursor_pipelined<SF, kInjectU>(P.syn, s_beg, s_len, nb, P.lanes, [&](int tg, int d, int wq) {
+        deliver_chunks_pipelined<SF, kInjectU>(P.syn, s_row, nb, P.lanes, [&](int tg, int d, int wq) {
             atomicAdd(ring + static_cast<int>((n - 1 + d) & mask) * tmax + tg, wq);
         });
         __syncthreads();
     }
-    // add the staged ring into the global one, kRingBatch slots in flight
-    for (int s0 = 0; s0 < R; s0 += kRingBatch)
-        for (int q = l; q < tlen; q += nthr) {
-            int v[kRingBatch], g[kRingBatch];
+    // add the staged ring into the global one: the tile's R x tlen cells dealt
+    // to all threads in order (coalesced within a slot), kInjWriteBack cells'
+    // loads in flight per thread; cells that received nothing are left alone.
+    // Thread l's cells are c = l + j nthr, walked as (slot, neuron) pairs.
+    const int cells = R * tlen, ds = nthr / tlen, dq = nthr - ds * tlen;
+    int slot = l / tlen, q = l - slot * tlen;
+    for (int c0 = 0; c0 < cells; c0 += kInjWriteBack * nthr) {
+        int v[kInjWriteBack], g[kInjWriteBack], s_k[kInjWriteBack], q_k[kInjWriteBack];
 #pragma unroll
-            for (int k = 0; k < kRingBatch; ++k) {
-                v[k] = s0 + k < R ? ring[(s0 + k) * tmax + q] : 0;
-                g[k] = v[k] ? B.ring[static_cast<size_t>(s0 + k) * B.n + td.t0 + q] : 0;
+        for (int k = 0; k < kInjWriteBack; ++k) {
+            s_k[k] = slot;
+            q_k[k] = q;
+            v[k] = slot < R ? ring[slot * tmax + q] : 0;
+            g[k] = v[k] ? B.ring[static_cast<int64_t>(slot) * B.n + td.t0 + q] : 0;
+            slot += ds;
+            q += dq;
+            if (q >= tlen) {
+                q -= tlen;
+                ++slot;
             }
-#pragma unroll
-            for (int k = 0; k < kRingBatch; ++k)
-                if (v[k]) B.ring[static_cast<size_t>(s0 + k) * B.n + td.t0 + q] = g[k] + v[k];
         }
+#pragma unroll
+        for (int k = 0; k < kInjWriteBack; ++k)
+            if (v[k]) B.ring[static_cast<int64_t>(s_k[k]) * B.n + td.t0 + q_k[k]] = g[k] + v[k];
+    }
 }
 
 // Fallback: one wavefront per listed neuron's row chunk of `seg` synapses,
