@@ -328,7 +328,9 @@ int mc_set_stream(struct mc_net *net, void *hip_stream);
 /*
  * Kernel timing with HIP events on the network's stream: enable (1) or disable (0)
  * timing of the dominant kernel; mc_get_timing returns the summed duration in ms
- * and the number of launches timed since it was enabled.
+ * and the number of launches timed since it was enabled.  Enabling records and
+ * queries each of the library's event pairs once (waiting for the network's
+ * stream), so that their first-use cost falls outside the runs it times.
  */
 int mc_set_timing(struct mc_net *net, int32_t on);
 int mc_get_timing(struct mc_net *net, double *kernel_ms, int64_t *launches);

@@ -53,6 +53,7 @@ int fail(int code, const std::string &msg)
 
 constexpr int64_t kSegMin = 100, kSegMax = 10000;   // steps between recorder drains
 constexpr int64_t kAbsorbSerial = 4096;             // records folded in on the calling thread alone
+constexpr size_t kUnreadPrefault = 16384;           // spike-list entries per network allocated and touched at build
 constexpr double kTuneMargin = 0.03;                // the autotuner switches only for a gain this large
 // Tile words carry (n mod 32767) + 1: words left by earlier launches can be
 // taken for a new launch's only if the step index jumped ahead by about 2^15.
@@ -188,6 +189,9 @@ struct mc_net {
     // host-side run state
     int64_t step = 0;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> unread;   // per instance
+    // unread[j][0 .. counted[j]) have their out-degrees in inst_events[j]; the
+    // rest are counted when the counters, the spikes or a snapshot are read
+    std::vector<size_t> counted;
     std::vector<int64_t> inst_spikes, inst_events, inst_max_step;
     std::vector<int32_t> absorb_scratch;            // per-step spike counts of a short record
     std::vector<int64_t> inst_dropped;  // events dropped by the step budget, per instance
@@ -393,12 +397,16 @@ int upload(mc_net *nt, const mc_config *cfg, const std::vector<mc::SynSeg> *segs
         hipError_t e = hipMalloc(&nt->rblk[b], bytes);
         if (e != hipSuccess) return fail(MC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         HIP_TRY(hipHostMalloc(&nt->h_rblk[b], bytes, hipHostMallocDefault));
+        // touched once here: the host's first access to a page of pinned memory
+        // faults it in (~60 us for the head's page in a first run)
+        std::memset(nt->h_rblk[b], 0, bytes);
         HIP_TRY(hipMemset(nt->rblk[b], 0, sizeof(mc::RecHead)));
         nt->rec[b] = reinterpret_cast<uint64_t *>(static_cast<char *>(nt->rblk[b]) + sizeof(mc::RecHead));
         nt->h_rec[b] = reinterpret_cast<uint64_t *>(static_cast<char *>(nt->h_rblk[b]) + sizeof(mc::RecHead));
         HIP_TRY(hipHostGetDevicePointer(&nt->hd_rblk[b], nt->h_rblk[b], 0));
     }
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_ctl), sizeof(mc::StepCtl), hipHostMallocDefault));
+    std::memset(nt->h_ctl, 0, sizeof(mc::StepCtl));
 
     // Static data.
     HIP_TRY(hipMemcpy(nt->meta, H.meta.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -537,6 +545,7 @@ int setup_tiled(mc_net *nt, int target, int ring_mode)
     if ((rc = dalloc(&nt->dropped, 2 * static_cast<size_t>(T))) || (rc = dalloc(&nt->abort_word, 1))) return rc;
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&nt->h_dropped), 2 * static_cast<size_t>(T) * sizeof(unsigned long long),
                           hipHostMallocDefault));
+    std::memset(nt->h_dropped, 0, 2 * static_cast<size_t>(T) * sizeof(unsigned long long));
     if (!sh.lds_ring) {
         nt->gstride = ((tile_max + 31) / 32) * 32;
         if ((rc = dalloc(&nt->gring, static_cast<size_t>(T) * nt->host.ring * nt->gstride))) return rc;
@@ -646,6 +655,13 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
     std::vector<uint16_t>().swap(nt->host.w16);
     std::vector<uint8_t>().swap(nt->host.d);
     nt->unread.assign(n, {});
+    nt->counted.assign(n, 0);
+    // capacity for the spikes of a few hundred steps, its pages touched now
+    // rather than by the first run that records that many
+    for (auto &v : nt->unread) {
+        v.resize(std::max<size_t>(1024, kUnreadPrefault / static_cast<size_t>(n)));
+        v.clear();
+    }
     nt->inst_spikes.assign(n, 0);
     nt->inst_events.assign(n, 0);
     nt->inst_dropped.assign(n, 0);
@@ -665,6 +681,26 @@ int build_common(const uint64_t *seeds, const double *scales, int32_t n, const m
     return MC_OK;
 }
 
+
+// Add the out-degrees of the recorded spikes not yet counted to their
+// instances' event counts.  A short run leaves this to the calls that read the
+// counters, the spikes or a snapshot: it reads the row pointers at random
+// places, which a run of a few steps would otherwise pay for from a cold cache.
+void settle_events(mc_net *nt)
+{
+    const auto &rp = nt->host.row_ptr;
+    for (int j = 0; j < nt->host.n_inst; ++j) {
+        const auto &v = nt->unread[static_cast<size_t>(j)];
+        const int64_t off = nt->host.inst_off[j];
+        int64_t ev = 0;
+        for (size_t q = nt->counted[static_cast<size_t>(j)]; q < v.size(); ++q) {
+            const int64_t gid = off + v[q].second;
+            ev += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
+        }
+        nt->inst_events[static_cast<size_t>(j)] += ev;
+        nt->counted[static_cast<size_t>(j)] = v.size();
+    }
+}
 
 // Fold the spikes of the steps [s0, s0 + span) that a recorder holds (`total`
 // recorded, `flags` of the launch, host copy `recs`) into the per-instance
@@ -689,7 +725,6 @@ int absorb(mc_net *nt, int64_t total, uint32_t flags, const uint64_t *recs, int6
             const int64_t n = static_cast<int64_t>(recs[q] >> 32);
             nt->unread[inst].emplace_back(n, gid - nt->host.inst_off[inst]);
             nt->inst_spikes[inst] += 1;
-            nt->inst_events[inst] += static_cast<int64_t>(rp[gid + 1] - rp[gid]);
             const int64_t k = n - s0;
             if (k >= 0 && k < span) per[static_cast<size_t>(k) * n_inst + inst] += 1;
         }
@@ -761,6 +796,7 @@ int absorb(mc_net *nt, int64_t total, uint32_t flags, const uint64_t *recs, int6
         f(0);
         for (auto &th : pool) th.join();
     };
+    settle_events(nt);
     parallel(count);
     for (int j = 0; j < n_inst; ++j) {
         int64_t off = static_cast<int64_t>(nt->unread[j].size());
@@ -771,6 +807,7 @@ int absorb(mc_net *nt, int64_t total, uint32_t flags, const uint64_t *recs, int6
             nt->inst_events[j] += part[static_cast<size_t>(t)].ev[j];
         }
         nt->unread[j].resize(static_cast<size_t>(off));
+        nt->counted[j] = static_cast<size_t>(off);
     }
     parallel(place);
     std::vector<int32_t> &per_step = part[0].per_step, &per_inst_step = part[0].per_inst_step;
@@ -1041,6 +1078,7 @@ int take_snapshot(mc_net *nt, Snapshot &s)
     HIP_TRY(hipMemcpy(&s.ctl, nt->ctl, sizeof(s.ctl), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(s.pois.data(), nt->pois_acc, s.pois.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     s.step = nt->step;
+    settle_events(nt);
     s.unread = nt->unread;
     s.inst_spikes = nt->inst_spikes;
     s.inst_events = nt->inst_events;
@@ -1062,6 +1100,7 @@ int restore_snapshot(mc_net *nt, const Snapshot &s)
     HIP_TRY(hipMemcpy(nt->pois_acc, s.pois.data(), s.pois.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
     nt->step = s.step;
     nt->unread = s.unread;
+    for (size_t j = 0; j < nt->unread.size(); ++j) nt->counted[j] = nt->unread[j].size();
     nt->inst_spikes = s.inst_spikes;
     nt->inst_events = s.inst_events;
     nt->inst_dropped = s.inst_dropped;
@@ -1418,12 +1457,14 @@ int mc_get_spikes(mc_net *net, int32_t instance, int64_t *steps_out, int32_t *id
     *count_out = static_cast<int64_t>(v.size());
     if (cap < static_cast<int64_t>(v.size())) return fail(MC_ERR_BUFFER_TOO_SMALL, "buffer too small");
     if (!v.empty() && (!steps_out || !ids_out)) return fail(MC_ERR_ARG, "output buffers must not be NULL");
+    settle_events(net);
     std::sort(v.begin(), v.end());
     for (size_t q = 0; q < v.size(); ++q) {
         steps_out[q] = v[q].first;
         ids_out[q] = v[q].second;
     }
     v.clear();
+    net->counted[static_cast<size_t>(instance)] = 0;
     return MC_OK;
 }
 
@@ -1485,6 +1526,7 @@ int mc_get_counters(mc_net *net, int32_t instance, mc_counters *out)
     std::vector<unsigned long long> acc(static_cast<size_t>(net->pois_slots));
     HIP_TRY(hipStreamSynchronize(net->stream));
     HIP_TRY(hipMemcpy(acc.data(), net->pois_acc, acc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    settle_events(net);
     out->steps = net->step;
     out->spikes = 0;
     out->events = 0;
@@ -1706,6 +1748,20 @@ int mc_inject_spikes_noalloc(mc_net *net, int32_t instance, const int32_t *ids, 
 int mc_set_timing(mc_net *net, int32_t on)
 {
     if (!net) return fail(MC_ERR_ARG, "net must not be NULL");
+    if (on && !net->timing) {
+        LIVE_OR_FAIL(net);
+        // The first elapsed-time query of an event pair costs the runtime some
+        // tens of microseconds: pay it here for every pair a run may use, not
+        // inside the first timed run.
+        for (int b = 0; b < 3; ++b) {
+            hipEvent_t e0 = b < 2 ? net->seg_ev0[b] : net->ev0, e1 = b < 2 ? net->seg_ev1[b] : net->ev1;
+            float ms = 0.f;
+            HIP_TRY(hipEventRecord(e0, net->stream));
+            HIP_TRY(hipEventRecord(e1, net->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        }
+    }
     net->timing = on != 0;
     net->kernel_ms = 0.0;
     net->launches = 0;
