@@ -651,15 +651,18 @@ __device__ __forceinline__ unsigned long long deliver_chunks_pipelined(const voi
     int q = l / G;
     const int r = l - q * G;
     if (q >= groups) return 0;
-    int j0 = 0, lo = 0, hi = 0, c0 = 0, nch = 0;       // sub-row [lo, hi): chunks c0 .. c0 + nch - 1
+    // sub-row [lo, hi): chunks c0 .. c0 + nch - 1 (record indices are unsigned
+    // 32-bit: a store may hold up to 2^32 - 1 records)
+    int j0 = 0, nch = 0;
+    uint32_t lo = 0, hi = 0, c0 = 0;
     auto next_row = [&](int from) {
         for (q = from; q < nb; q += groups) {
             const int2 row = s_row[q];
             if (row.y > 0) {
-                lo = row.x;
-                hi = lo + row.y;
+                lo = static_cast<uint32_t>(row.x);
+                hi = lo + static_cast<uint32_t>(row.y);
                 c0 = lo / P;
-                nch = (hi - 1) / P + 1 - c0;
+                nch = static_cast<int>((hi - 1) / P + 1 - c0);
                 return;
             }
         }
@@ -675,9 +678,11 @@ __device__ __forceinline__ unsigned long long deliver_chunks_pipelined(const voi
             idx[k] = 0u;
             if (q < nb) {
                 if (j0 + r < nch) {
-                    const int c = c0 + j0 + r, first = max(lo - c * P, 0), last = min(hi - c * P, P);
+                    const uint32_t c = c0 + static_cast<uint32_t>(j0 + r), base = c * P;   // base <= hi - 1
+                    const int first = lo > base ? static_cast<int>(lo - base) : 0;
+                    const int last = hi - base < static_cast<uint32_t>(P) ? static_cast<int>(hi - base) : P;
                     m[k] = ((1 << last) - 1) & ~((1 << first) - 1);
-                    idx[k] = static_cast<uint32_t>(c);
+                    idx[k] = c;
                 }
                 j0 += G;
                 if (j0 >= nch) {
