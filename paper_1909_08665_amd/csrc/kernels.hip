@@ -589,12 +589,13 @@ __device__ __forceinline__ unsigned long long deliver_cursor(const void *__restr
     int q = l / G;
     const int r = l - q * G;
     if (q >= groups) return 0;                         // lanes past the last whole group
-    int j0 = 0, len = 0, beg = 0;
+    int j0 = 0, len = 0;
+    uint32_t beg = 0;                                  // record indices are unsigned 32-bit
     auto next_row = [&](int from) {                    // the group's next spike with records, from `from` on
         for (q = from; q < nb; q += groups) {
             len = s_len[q];
             if (len > 0) {
-                beg = s_beg[q];
+                beg = static_cast<uint32_t>(s_beg[q]);
                 return;
             }
         }
@@ -607,7 +608,7 @@ __device__ __forceinline__ unsigned long long deliver_cursor(const void *__restr
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             v[k] = q < nb && j0 + r < len;
-            idx[k] = v[k] ? static_cast<uint32_t>(beg + j0 + r) : 0u;
+            idx[k] = v[k] ? beg + static_cast<uint32_t>(j0 + r) : 0u;
             if (q < nb) {
                 j0 += G;
                 if (j0 >= len) {
