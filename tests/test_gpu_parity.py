@@ -510,6 +510,43 @@ def test_checkpoint_resume_is_bit_exact(conn, tmp_path):
     assert e.value.code == -1
 
 
+def test_event_counts_with_undrained_spikes(conn, tmp_path):
+    """A short record's event counts (sums of the spiking neurons' out-degrees)
+    are taken when they are read: counters read while spikes are still waiting
+    to be drained, after a checkpoint saved with spikes waiting, and per
+    instance of a batch all equal the oracle's."""
+    _say("event counts with undrained spikes")
+    path = str(tmp_path / "pending.ckpt")
+    net = mc.Network.build(43, 0.05, conn)
+    orc = _oracle(43, 0.05, conn)
+    keys = ("steps", "spikes", "events", "max_spikes_per_step")
+    for steps in (7, 40, 300):
+        net.run(steps)
+        orc.run(steps)
+        c, rc = net.counters(), orc.counters()
+        assert all(c[k] == rc[k] for k in keys), (c, rc)
+    assert c["events"] > 0
+    net.save(path)                      # spikes of 347 steps still undrained
+    other = mc.Network.build(43, 0.05, conn)
+    other.load(path)
+    assert other.counters() == net.counters()
+    st, ids = other.spikes()
+    assert len(st) == c["spikes"]
+    assert _same_run(net, orc) == c["spikes"]
+    net.run(200)
+    orc.run(200)
+    c, rc = net.counters(), orc.counters()
+    assert all(c[k] == rc[k] for k in keys), (c, rc)
+    # per instance: instance 1 of a batch against its own oracle
+    batch = mc.Network.build_batch([43, 44], [0.05, 0.02], conn)
+    o1 = _oracle(44, 0.02, conn)
+    batch.run(250)
+    o1.run(250)
+    c1, r1 = batch.counters(1), o1.counters()
+    assert c1["spikes"] == r1["spikes"] and c1["events"] == r1["events"]
+    assert batch.counters()["events"] == c1["events"] + batch.counters(0)["events"]
+
+
 def test_rewind_then_new_dynamics(conn, tmp_path):
     """Loading a checkpoint moves the step index back; the spike-exchange words
     written for the abandoned steps carry the tags the resumed run polls for and
