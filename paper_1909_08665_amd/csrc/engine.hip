@@ -1099,8 +1099,11 @@ int restore_snapshot(mc_net *nt, const Snapshot &s)
     HIP_TRY(hipMemcpy(nt->ctl, &s.ctl, sizeof(s.ctl), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(nt->pois_acc, s.pois.data(), s.pois.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
     nt->step = s.step;
-    nt->unread = s.unread;
-    for (size_t j = 0; j < nt->unread.size(); ++j) nt->counted[j] = nt->unread[j].size();
+    for (size_t j = 0; j < nt->unread.size(); ++j) {
+        // element-wise, keeping each list's capacity (touched at build)
+        nt->unread[j].assign(s.unread[j].begin(), s.unread[j].end());
+        nt->counted[j] = nt->unread[j].size();
+    }
     nt->inst_spikes = s.inst_spikes;
     nt->inst_events = s.inst_events;
     nt->inst_dropped = s.inst_dropped;
